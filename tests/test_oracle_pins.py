@@ -1,0 +1,478 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: numbers the
+paper prints (tests/golden/paper_constants.json), closed forms written from a
+different route (Gaussian moments, the App. B closed form, Lagrange
+interpolation identities), numpy/mpmath library routines on the literal
+matrices of eq. (2), invariances (uniform flow, Galilean shift, conservation of
+the collision) and the exact Riemann solution.
+"""
+import json
+import math
+import os
+
+import mpmath as mp
+import numpy as np
+import pytest
+
+import oracle
+from oracle import riemann
+from paper_1806_05089_amd import workloads
+
+GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_constants.json")))
+
+
+# ---------------------------------------------------------------- P1: quadrature
+@pytest.mark.parametrize("q,exact_deg", [(4, 7), (3, 5)])
+def test_lattice_gauss_hermite_exactness(q, exact_deg):
+    c, w, TL = oracle.lattice(q)
+    assert abs(w.sum() - 1.0) < 1e-15
+    for k in range(exact_deg + 1):
+        # E[X^k] for X ~ N(0, T_L): (k-1)!! T_L^(k/2) for even k, 0 for odd k
+        exact = 0.0 if k % 2 else float(np.prod(np.arange(k - 1, 0, -2))) * TL ** (k // 2)
+        assert abs(np.sum(w * c ** k) - exact) < 1e-13, (q, k)
+    # one degree beyond the rule is no longer exact
+    k = exact_deg + 1
+    exact = float(np.prod(np.arange(k - 1, 0, -2))) * TL ** (k // 2)
+    assert abs(np.sum(w * c ** k) - exact) > 1e-3
+
+
+def test_d2q16_matches_numpy_hermegauss():
+    x, wt = np.polynomial.hermite_e.hermegauss(4)
+    c, w, TL = oracle.lattice(4)
+    assert TL == 1.0
+    assert np.allclose(np.sort(c), np.sort(x), atol=1e-14, rtol=0)
+    assert np.allclose(w[np.argsort(c)], wt[np.argsort(x)] / math.sqrt(2 * math.pi), atol=1e-15)
+
+
+def test_d2q9_constants_from_paper():
+    gd = GOLDEN["d2q9"]
+    c, w, TL = oracle.lattice(3)
+    assert np.allclose(c, gd["c"], atol=0, rtol=0)
+    assert np.allclose(w, gd["W"], atol=1e-16)
+    assert abs(TL - gd["T_L"]) < 1e-16
+
+
+# -------------------------------------------------- P2: transfer matrix (eq. 4)
+def _literal_M(q, ux, uy, T):
+    """Eq. (2): M[(m,n),(i,j)] = (sqrt(theta) c_i + u_x)^m (sqrt(theta) c_j + u_y)^n."""
+    c, _, TL = oracle.lattice(q)
+    s = math.sqrt(T / TL)
+    vx = s * c + ux
+    vy = s * c + uy
+    M = np.zeros((q * q, q * q))
+    for m in range(q):
+        for n in range(q):
+            for i in range(q):
+                for j in range(q):
+                    M[m * q + n, i * q + j] = vx[i] ** m * vy[j] ** n
+    return M
+
+
+GAUGE_PAIRS = [
+    ((0.0, 0.0, 1.0), (0.1, -0.05, 1.2)),
+    ((0.3, 0.2, 0.8), (-0.2, 0.4, 1.1)),
+    ((0.05, -0.02, 1.0), (0.0, 0.0, 1.0)),
+]
+
+
+@pytest.mark.parametrize("src,dst", GAUGE_PAIRS)
+def test_transfer_equals_literal_moment_solve(src, dst):
+    """G = M_dst^-1 M_src with the literal monomials of eq. (2), at moderate gauges."""
+    for q in (4, 3):
+        G_lit = np.linalg.solve(_literal_M(q, *dst), _literal_M(q, *src))
+        G2 = oracle.transfer_2d(q, src, dst)
+        assert np.max(np.abs(G2 - G_lit)) < 1e-10, q
+
+
+@pytest.mark.parametrize("src,dst", [((5.0, 0.0, 1.0), (5.3, -0.2, 0.8)),
+                                     ((100.0, -40.0, 2.0), (100.5, -40.2, 1.5)),
+                                     ((0.0, 0.0, 4.0), (1.0, 2.0, 0.5))])
+def test_transfer_high_mach_vs_mpmath(src, dst):
+    """Ill-conditioned in absolute monomials: compare against a 50-digit solve of eq. (4)."""
+    mp.mp.dps = 50
+    q = 4
+    r6 = mp.sqrt(6)
+    c = [-mp.sqrt(3 + r6), -mp.sqrt(3 - r6), mp.sqrt(3 - r6), mp.sqrt(3 + r6)]
+
+    def M(ux, uy, T):
+        s = mp.sqrt(mp.mpf(T))
+        A = mp.matrix(16, 16)
+        for m in range(4):
+            for n in range(4):
+                for i in range(4):
+                    for j in range(4):
+                        A[m * 4 + n, i * 4 + j] = (s * c[i] + ux) ** m * (s * c[j] + uy) ** n
+        return A
+
+    Gm = mp.inverse(M(*dst)) * M(*src)
+    G_ref = np.array([[float(Gm[a, b]) for b in range(16)] for a in range(16)])
+    G2 = oracle.transfer_2d(q, src, dst)
+    Gx = oracle.transfer_1d(q, src[0], src[2], dst[0], dst[2])
+    Gy = oracle.transfer_1d(q, src[1], src[2], dst[1], dst[2])
+    scale = max(1.0, np.max(np.abs(G_ref)))
+    assert np.max(np.abs(G2 - G_ref)) / scale < 1e-12
+    assert np.max(np.abs(np.kron(Gx, Gy) - G_ref)) / scale < 1e-12
+
+
+def test_kronecker_factorisation():
+    rng = np.random.default_rng(0)
+    for q in (4, 3):
+        for _ in range(5):
+            src = (rng.normal(), rng.normal(), rng.uniform(0.3, 2.0))
+            dst = (rng.normal(), rng.normal(), rng.uniform(0.3, 2.0))
+            G2 = oracle.transfer_2d(q, src, dst)
+            Gx = oracle.transfer_1d(q, src[0], src[2], dst[0], dst[2])
+            Gy = oracle.transfer_1d(q, src[1], src[2], dst[1], dst[2])
+            assert np.max(np.abs(G2 - np.kron(Gx, Gy))) < 1e-11
+
+
+def test_transfer_is_lagrange_interpolation_on_target_speeds():
+    """Per axis, matching q moments means G[k, i] = l_k(z_i) with l_k the Lagrange
+    basis on the target speeds and z_i the source speeds seen from the target frame."""
+    rng = np.random.default_rng(1)
+    for q in (4, 3):
+        c, _, TL = oracle.lattice(q)
+        for _ in range(5):
+            us, Ts, ud, Td = rng.normal(), rng.uniform(0.3, 2), rng.normal(), rng.uniform(0.3, 2)
+            z = (math.sqrt(Ts / TL) * c + us - ud) / math.sqrt(Td / TL)
+            L = np.zeros((q, q))
+            for k in range(q):
+                for i in range(q):
+                    L[k, i] = np.prod([(z[i] - c[m]) / (c[k] - c[m]) for m in range(q) if m != k])
+            G = oracle.transfer_1d(q, us, Ts, ud, Td)
+            assert np.max(np.abs(G - L)) < 1e-12
+
+
+def test_appendix_b_closed_form_d2q9():
+    """App. B closed form (D2Q9, T_L = 1/3) with both temperatures in B(i, j) read as
+    the target T' and omega(i != 0) = -1/(2T'): equals the oracle's transfer.  As
+    printed (B with the source T) it agrees only when T = T'."""
+    def closed_form(f, src, dst, B_uses_target=True):
+        ux, uy, T = src
+        uxp, uyp, Tp = dst
+        idx = [-1, 0, 1]
+        TB = Tp if B_uses_target else T
+
+        def g(up, u, i, j):
+            A = (up - u) / math.sqrt(3.0) - i * math.sqrt(T)
+            B = TB if j == 0 else j * math.sqrt(TB) * A
+            return A * A - B
+
+        def omega(i):
+            return 1.0 / Tp if i == 0 else -1.0 / (2.0 * Tp)
+
+        out = np.zeros(9)
+        for kk, k in enumerate(idx):
+            for ll, l in enumerate(idx):
+                acc = 0.0
+                for ii, i in enumerate(idx):
+                    for jj, j in enumerate(idx):
+                        acc += g(uxp, ux, i, k) * g(uyp, uy, j, l) * f[ii * 3 + jj]
+                out[kk * 3 + ll] = omega(k) * omega(l) * acc
+        return out
+
+    rng = np.random.default_rng(2)
+    for _ in range(5):
+        src = (rng.normal(0, 0.3), rng.normal(0, 0.3), rng.uniform(0.2, 0.6))
+        dst = (rng.normal(0, 0.3), rng.normal(0, 0.3), rng.uniform(0.2, 0.6))
+        f = rng.uniform(0.05, 0.3, 9)
+        G = oracle.transfer_2d(3, src, dst)
+        assert np.max(np.abs(closed_form(f, src, dst) - G @ f)) < 1e-12
+        assert np.max(np.abs(closed_form(f, src, dst, B_uses_target=False) - G @ f)) > 1e-6
+    iso = (0.1, -0.2, 0.4)
+    iso2 = (-0.3, 0.05, 0.4)
+    f = rng.uniform(0.05, 0.3, 9)
+    assert np.max(np.abs(closed_form(f, iso, iso2, False) - oracle.transfer_2d(3, iso, iso2) @ f)) < 1e-12
+
+
+# --------------------------------------------------------- P3, P4: identities
+def test_round_trip_composition_and_column_sums():
+    rng = np.random.default_rng(3)
+    for q in (4, 3):
+        for _ in range(5):
+            a = (rng.normal(0, 0.5), rng.normal(0, 0.5), rng.uniform(0.5, 1.5))
+            b = (rng.normal(0, 0.5), rng.normal(0, 0.5), rng.uniform(0.5, 1.5))
+            c = (rng.normal(0, 0.5), rng.normal(0, 0.5), rng.uniform(0.5, 1.5))
+            Gab, Gba = oracle.transfer_2d(q, a, b), oracle.transfer_2d(q, b, a)
+            Gbc, Gac = oracle.transfer_2d(q, b, c), oracle.transfer_2d(q, a, c)
+            I = np.eye(q * q)
+            assert np.max(np.abs(Gba @ Gab - I)) < 1e-11
+            assert np.max(np.abs(Gbc @ Gab - Gac)) < 1e-11
+            assert np.max(np.abs(Gab.sum(axis=0) - 1.0)) < 1e-12  # mass
+
+
+def test_matched_moments_preserved():
+    """Eq. (3): M_lambda' G f = M_lambda f for the Q moments of eq. (2)."""
+    rng = np.random.default_rng(4)
+    for q in (4, 3):
+        for _ in range(5):
+            a = (rng.normal(0, 0.5), rng.normal(0, 0.5), rng.uniform(0.5, 1.5))
+            b = (rng.normal(0, 0.5), rng.normal(0, 0.5), rng.uniform(0.5, 1.5))
+            f = rng.uniform(0.01, 0.2, q * q)
+            Ma, Mb = _literal_M(q, *a), _literal_M(q, *b)
+            lhs = Mb @ (oracle.transfer_2d(q, a, b) @ f)
+            rhs = Ma @ f
+            assert np.max(np.abs(lhs - rhs)) / np.max(np.abs(rhs)) < 1e-12
+
+
+# ------------------------------------------------- P5, P6: equilibrium (App. A)
+def _gauss_moment(u, T, m):
+    """E[(u + sqrt(T) X)^m], X ~ N(0, 1)."""
+    acc = 0.0
+    for k in range(0, m + 1, 2):
+        acc += math.comb(m, k) * u ** (m - k) * T ** (k / 2) * float(np.prod(np.arange(k - 1, 0, -2)))
+    return acc
+
+
+def test_equilibrium_has_maxwellian_moments_d2q16():
+    c, w, TL = oracle.lattice(4)
+    for (ux, uy, T) in ((0.0, 0.0, 1.0), (3.0, -1.0, 0.5), (50.0, 20.0, 4.0)):
+        s = math.sqrt(T / TL)
+        for m in range(8):
+            lat = float(np.sum(w * (s * c + ux) ** m))
+            ref = _gauss_moment(ux, T, m)
+            assert abs(lat - ref) <= 1e-12 * max(1.0, abs(ref)), (ux, T, m)
+    # through the oracle: raw moments of the initial state
+    rho = np.full((2, 3), 1.3)
+    f, g = oracle.init(rho, np.full((2, 3), 0.7), np.full((2, 3), -0.4), np.full((2, 3), 0.9))
+    _, _, _, _, M = oracle.moments(f, g, with_raw=True)
+    for m in range(4):
+        for n in range(4):
+            ref = 1.3 * _gauss_moment(0.7, 0.9, m) * _gauss_moment(-0.4, 0.9, n)
+            assert np.allclose(M[m * 4 + n], ref, rtol=1e-13, atol=1e-14)
+
+
+def test_d2q9_equilibrium_in_lattice_gauge_is_product_form():
+    """G_lambda^{lambda_L} (rho W) = rho Psi(u_x) Psi(u_y), Psi_0 = 1 - u^2 - T,
+    Psi_(+-1) = (u^2 + T +- u) / 2 (D2Q9, T_L = 1/3)."""
+    _, w, TL = oracle.lattice(3)
+    rng = np.random.default_rng(5)
+    for _ in range(5):
+        ux, uy, T, rho = rng.normal(0, 0.2), rng.normal(0, 0.2), rng.uniform(0.2, 0.5), 1.3
+        G = oracle.transfer_2d(3, (ux, uy, T), (0.0, 0.0, TL))
+        feq = rho * np.outer(w, w).ravel()
+
+        def psi(u):
+            return np.array([(u * u + T - u) / 2, 1 - u * u - T, (u * u + T + u) / 2])
+
+        ref = rho * np.outer(psi(ux), psi(uy)).ravel()
+        assert np.max(np.abs(G @ feq - ref)) < 1e-13
+
+
+# ------------------------------------------------------ P7: Lagrange weights
+def test_lagrange_weights():
+    ts = np.linspace(1.0, 2.0, 11)[:-1]
+    for t in ts:
+        a = np.array([oracle.lagrange_weight(t, n) for n in range(4)])
+        assert abs(a.sum() - 1.0) < 1e-14
+        for p in range(4):
+            assert abs(np.sum(a * np.arange(4) ** p) - t ** p) < 1e-13
+    assert np.allclose([oracle.lagrange_weight(1.0, n) for n in range(4)], [0, 1, 0, 0], atol=0)
+    # continuity across a floor switch: x -> 2^- (stencil origin x0) equals x0+1 stencil at t = 1
+    a_left = np.array([oracle.lagrange_weight(2.0 - 1e-13, n) for n in range(4)])
+    assert np.allclose(a_left, [0, 0, 1, 0], atol=1e-12)
+
+
+# ------------------------------------------------------- P8: uniform flow
+@pytest.mark.parametrize("ux,uy,T", [(0.0, 0.0, 1.0), (5.0, 0.0, 1.0), (100.0, -30.0, 0.5),
+                                     (0.3, 0.2, 1e-4), (2.0, 1.0, 100.0)])
+def test_uniform_flow_stays_uniform(ux, uy, T):
+    w = workloads.uniform(6, 5, rho=1.2, ux=ux, uy=uy, T=T)
+    f, g = oracle.init(w.rho, w.ux, w.uy, w.T)
+    f0, g0 = f.copy(), g.copy()
+    cfg = oracle.OracleConfig(tau=0.7)
+    for _ in range(3):
+        f, g, it, st = oracle.step(f, g, cfg)
+        assert np.all(it == 1) and np.all(st == 0)
+    assert np.max(np.abs(f - f0)) < 1e-12
+    umag = max(1.0, math.hypot(ux, uy))
+    assert np.max(np.abs(g[:2] - g0[:2])) < 1e-13 * umag
+    assert np.max(np.abs(g[2] - g0[2])) < 1e-12 * max(T, umag ** 2 * 1e-2)
+
+
+# ------------------------------------------- P9: integer-shift Galilean shift
+def test_galilean_integer_shift_mach5():
+    """At T = T_L (sqrt(theta) = 1) a boost by U = 5 moves every departure point by
+    exactly 5 nodes: the boosted run equals the rest run rolled by 5 n."""
+    N = 20
+    w0 = workloads.mach5(N, U=0.0, seed=0)
+    wU = workloads.mach5(N, U=5.0, seed=0)
+    cfg = oracle.OracleConfig(fixed_iter=3, tau=0.6)
+    f0, g0 = oracle.init(w0.rho, w0.ux, w0.uy, w0.T)
+    fU, gU = oracle.init(wU.rho, wU.ux, wU.uy, wU.T)
+    for n in range(1, 4):
+        f0, g0, _, _ = oracle.step(f0, g0, cfg)
+        fU, gU, _, _ = oracle.step(fU, gU, cfg)
+        sh = (5 * n) % N
+        assert np.max(np.abs(np.roll(f0, sh, axis=2) - fU)) < 1e-13
+        assert np.max(np.abs(np.roll(g0[0], sh, axis=1) + 5.0 - gU[0])) < 1e-12
+        assert np.max(np.abs(np.roll(g0[1:], sh, axis=2) - gU[1:])) < 1e-12
+
+
+# --------------------------------------------- P10: collision conservation
+def test_collision_conserves_and_gauge_matches_moments():
+    w = workloads.random_smooth(12, 10, seed=6, mach=0.4)
+    f, g = oracle.init(w.rho, w.ux, w.uy, w.T)
+    for tau in (0.6, 1.0, 1.7):
+        fo, go, _, _ = oracle.step(f, g, oracle.OracleConfig(fixed_iter=1, tau=tau))
+        rho, ux, uy, T = oracle.moments(fo, go)
+        assert np.max(np.abs(ux - go[0])) < 1e-13
+        assert np.max(np.abs(uy - go[1])) < 1e-13
+        assert np.max(np.abs(T - go[2])) < 1e-13
+        if tau == 1.0:  # full relaxation: exactly rho W in the new gauge (eq. 17)
+            _, wq, _ = oracle.lattice(4)
+            W = np.outer(wq, wq).ravel()[:, None, None]
+            assert np.max(np.abs(fo - rho[None] * W)) < 1e-14
+    # isothermal: mass and momentum are conserved by the collision
+    fo, go, _, _ = oracle.step(f, g, oracle.OracleConfig(fixed_iter=1, tau=0.6, isothermal=1))
+    rho, ux, uy, T = oracle.moments(fo, go)
+    assert np.max(np.abs(ux - go[0])) < 1e-13 and np.max(np.abs(uy - go[1])) < 1e-13
+    assert np.array_equal(go[2], g[2])
+
+
+def test_single_pass_equals_definition_at_one_node():
+    """Brute-force one node of one pass from eq. (5)/(6) with explicit Q x Q transfer
+    matrices and compare to the oracle's fixed_iter=1 output before collision
+    (tau -> infinity removes BGK, rho W term vanishes)."""
+    w = workloads.random_smooth(9, 8, seed=12, mach=0.5)
+    f, g = oracle.init(w.rho, w.ux, w.uy, w.T)
+    # perturb f away from equilibrium so that every population matters
+    rng = np.random.default_rng(12)
+    f = f * (1.0 + 0.05 * rng.standard_normal(f.shape))
+    cfg = oracle.OracleConfig(fixed_iter=1, tau=1e300)
+    fo, go, _, _ = oracle.step(f, g, cfg)
+    c, _, TL = oracle.lattice(4)
+    X, Y = 3, 5
+    ux, uy, T = g[:, Y, X]
+    s = math.sqrt(T / TL)
+    ft = np.zeros(16)
+    for i in range(4):
+        for j in range(4):
+            xd, yd = X - (s * c[i] + ux), Y - (s * c[j] + uy)
+            x0, y0 = math.floor(xd) - 1, math.floor(yd) - 1
+            for m in range(4):
+                for n in range(4):
+                    ax = np.prod([((xd - x0) - k) / (n - k) for k in range(4) if k != n])
+                    ay = np.prod([((yd - y0) - k) / (m - k) for k in range(4) if k != m])
+                    sx, sy = (x0 + n) % 9, (y0 + m) % 8
+                    G = np.linalg.solve(_literal_M(4, ux, uy, T), _literal_M(4, *g[:, sy, sx]))
+                    ft[i * 4 + j] += ax * ay * (G @ f[:, sy, sx])[i * 4 + j]
+    # eqs. (10)-(12)
+    v = np.array([(s * c[i] + ux, s * c[j] + uy) for i in range(4) for j in range(4)])
+    rho = ft.sum()
+    u1 = (v * ft[:, None]).sum(0) / rho
+    T1 = ((v ** 2).sum(1) * ft).sum() / rho / 2 - (u1 ** 2).sum() / 2
+    assert abs(go[0, Y, X] - u1[0]) < 1e-11 and abs(go[1, Y, X] - u1[1]) < 1e-11
+    assert abs(go[2, Y, X] - T1) < 1e-11
+    G = np.linalg.solve(_literal_M(4, u1[0], u1[1], T1), _literal_M(4, ux, uy, T))
+    assert np.max(np.abs(fo[:, Y, X] - G @ ft)) < 1e-11
+
+
+# ------------------------------------------------- P11: seed independence
+def test_seed_independence():
+    w = workloads.random_smooth(12, 12, seed=7, mach=0.1)
+    f, g = oracle.init(w.rho, w.ux, w.uy, w.T)
+    outs = []
+    for mode in (0, 1, 2):
+        fo, go, it, st = oracle.step(f, g, oracle.OracleConfig(seed_mode=mode, max_iter=60))
+        assert np.all(st == 0)
+        outs.append((fo, go, it))
+    for fo, go, it in outs[1:]:
+        assert np.max(np.abs(go - outs[0][1])) < 1e-9
+        assert np.max(np.abs(fo - outs[0][0])) < 1e-9
+    # the natural seed needs the fewest passes
+    assert outs[0][2].mean() <= outs[1][2].mean() and outs[0][2].mean() <= outs[2][2].mean()
+
+
+# --------------------------------------------- physics: TGV viscosity, App. D
+def _tgv_nu(N, steps):
+    w = workloads.taylor_green(N)
+    f, g = oracle.init(w.rho, w.ux, w.uy, w.T)
+    cfg = oracle.OracleConfig(isothermal=1, tau=0.6)
+    E = []
+    for _ in range(steps):
+        f, g, it, st = oracle.step(f, g, cfg)
+        rho, ux, uy, _ = oracle.moments(f, g)
+        E.append(0.5 * np.sum(rho * (ux ** 2 + uy ** 2)))
+    t = np.arange(1, steps + 1)
+    slope = np.polyfit(t[steps // 4:], np.log(E[steps // 4:]), 1)[0]
+    k = 2 * math.pi / N
+    return -slope / (4 * k * k)  # kinetic energy decays at 4 nu k^2
+
+
+def test_taylor_green_viscosity_and_order():
+    nu_set = 1.0 * (0.6 - 0.5)  # nu = T (tau - 1/2)
+    e16 = abs(_tgv_nu(16, 60) / nu_set - 1)
+    e24 = abs(_tgv_nu(24, 120) / nu_set - 1)
+    assert e24 < 0.06
+    order = math.log(e16 / e24) / math.log(24 / 16)
+    assert order > 1.7, (e16, e24, order)
+
+
+# --------------------------------------------- physics: sound speed, gamma = 2
+def test_speed_of_sound():
+    nx, steps = 300, 50
+    x = np.arange(nx)
+    for T0, U in ((1.0, 0.0), (0.25, 0.0), (1.0, 1.0)):
+        p = T0 + 1e-3 * np.exp(-((x - 150) / 4.0) ** 2)
+        f, g = oracle.init(np.ones((1, nx)), np.full((1, nx), U), np.zeros((1, nx)), p[None])
+        for _ in range(steps):
+            f, g, _, _ = oracle.step(f, g, oracle.OracleConfig(tau=0.6))
+        rho, _, _, T = oracle.moments(f, g)
+        dp = (rho * T)[0] - T0
+        lo = 150 + int(U * steps)
+        k = np.argmax(dp[lo:]) + lo
+        y0, y1, y2 = dp[k - 1], dp[k], dp[k + 1]
+        peak = k + 0.5 * (y0 - y2) / (y0 - 2 * y1 + y2)
+        cs = (peak - 150 - U * steps) / steps
+        assert abs(cs / math.sqrt(GOLDEN["sound_speed"]["gamma"] * T0) - 1) < 0.01, (T0, U, cs)
+
+
+# --------------------------------------------- physics: Sod vs exact Riemann
+def test_sod_vs_exact_riemann():
+    nx, steps = 256, 100
+    w = workloads.sod(nx, 1)
+    f, g = oracle.init(w.rho, w.ux, w.uy, w.T)
+    cfg = oracle.OracleConfig(bc_x=1, tau=w.tau)
+    for _ in range(steps):
+        f, g, it, st = oracle.step(f, g, cfg)
+        assert not np.any(st == 2)
+    rho, ux, _, T = oracle.moments(f, g)
+    s = w.meta["scale"]
+    xi = (np.arange(nx) - w.meta["x_diaphragm"]) / steps
+    re, ue, pe = riemann.sample((1.0, 0.0, s * 1.0), (0.125, 0.0, s * 0.1), xi)
+    assert np.mean(np.abs(rho[0] - re)) < 0.01
+    assert np.mean(np.abs(ux[0] - ue)) < 0.02
+    assert np.mean(np.abs(rho[0] * T[0] - pe)) < 0.004
+    # the rarefaction (sound speed sqrt(gamma T), gamma = 2) lands on the exact
+    # solution: the rho = 0.9 level crossing within one node
+    assert abs(np.min(np.nonzero(rho[0] < 0.9)[0]) - np.min(np.nonzero(re < 0.9)[0])) <= 1
+    # the shock runs about 5 % slow at every resolution and tau: semi-Lagrangian
+    # advection is not conservative, so the Rankine-Hugoniot speed is not enforced
+    _, _, _, shock = riemann.wave_speeds((1.0, 0.0, s), (0.125, 0.0, 0.1 * s))
+    xs = w.meta["x_diaphragm"] + shock * steps
+    sim_shock = np.max(np.nonzero(rho[0] > 0.5 * (0.125 + 0.2043))[0])
+    assert -0.08 * shock * steps < sim_shock - xs < 0.0
+
+
+# --------------------------------------------- complex-step consistency
+def test_complex_step_matches_finite_difference():
+    w = workloads.random_smooth(8, 7, seed=9, mach=0.3)
+    f, g = oracle.init(w.rho, w.ux, w.uy, w.T)
+    rng = np.random.default_rng(9)
+    df = 1e-3 * rng.standard_normal(f.shape)
+    dg = 1e-2 * rng.standard_normal(g.shape)
+    cfg = oracle.OracleConfig(fixed_iter=3, tau=0.6)
+    h = 1e-30
+    fo_c, go_c, _, _ = oracle.step_cs(f + 1j * h * df, g + 1j * h * dg, cfg)
+    jvp_f, jvp_g = fo_c.imag / h, go_c.imag / h
+    e = 1e-6
+    fp, gp, _, _ = oracle.step(f + e * df, g + e * dg, cfg)
+    fm, gm, _, _ = oracle.step(f - e * df, g - e * dg, cfg)
+    fd_f, fd_g = (fp - fm) / (2 * e), (gp - gm) / (2 * e)
+    assert np.max(np.abs(jvp_f - fd_f)) / np.max(np.abs(fd_f)) < 1e-6
+    assert np.max(np.abs(jvp_g - fd_g)) / np.max(np.abs(fd_g)) < 1e-6
+    # real part of the complex run is the real run
+    fo, go, _, _ = oracle.step(f, g, cfg)
+    assert np.max(np.abs(fo_c.real - fo)) < 1e-14 and np.max(np.abs(go_c.real - go)) < 1e-14
