@@ -1,0 +1,201 @@
+"""Throughput of the PonD time step on one MI355X.
+
+Workload: the four-quadrant 2-D Riemann problem (D2Q16, zero-gradient edges,
+tau = 0.55, seed 3) on a 1024^2 grid, run from its initial state for K steps.
+A "step" is one pond_step launch: propagation with the predictor-corrector
+gauge iteration, then BGK.  MLUPS = nodes * steps / seconds / 1e6 with the
+state resident in HBM; timed with HIP events on the launch stream.
+
+Prints one JSON line (rank 0).  The FP64 path gives `value`; the FP32-mixed
+path, its error against FP64 and the adjoint/forward time ratio are reported
+beside it, with the oracle timed on host cores as `cpu_baseline`.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+import torch
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+from paper_1806_05089_amd import pond, workloads  # noqa: E402
+
+# Algorithmic flop count (see the design notes): per node and predictor-corrector
+# pass, 16 populations x 16 collocation points x 42 flops for the row-Kronecker
+# contraction and weighted accumulate, plus 16 x 16 x 64 flops for the two
+# transfer rows (4 entries x (linear map + cubic Horner) each); per node and
+# step, 560 flops for the regauge and the BGK relaxation.
+FLOPS_PER_NODE_PASS = 16 * 16 * 42 + 16 * 16 * 64
+FLOPS_PER_NODE_STEP = 560
+PEAK_FP64_TFLOPS = 78.6   # MI355X vector FP64: 256 CU x 2.4 GHz x 64 lanes x 2
+PEAK_FP32_TFLOPS = 157.3  # MI355X published FP32 peak
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def make_cfg(w, precision):
+    ny, nx = w.shape
+    cfg = pond.PondConfig(nx=nx, ny=ny, q1d=4, precision=precision, isothermal=w.isothermal,
+                          bc_x=w.bc_x, bc_y=w.bc_y, tau=w.tau, max_iter=20)
+    if precision == pond.POND_F32_MIXED:
+        cfg = cfg.replace(eps_abs=1e-6, eps_rel=1e-5)
+    return cfg
+
+
+def run_steps(cfg, w, steps, warmup, count_passes=False):
+    """Warm up on a throwaway copy, then time `steps` steps from the initial state."""
+    a = pond.init(cfg, w.rho, w.ux, w.uy, w.T)
+    b = pond.empty_state(cfg)
+    for _ in range(warmup):
+        pond.step(cfg, a, b)
+        a, b = b, a
+    a = pond.init(cfg, w.rho, w.ux, w.uy, w.T)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        pond.step(cfg, a, b)
+        a, b = b, a
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    passes = None
+    if count_passes:
+        # replay with per-step statistics to count the predictor-corrector passes
+        a = pond.init(cfg, w.rho, w.ux, w.uy, w.T)
+        total = 0.0
+        nonconv = 0
+        for _ in range(steps):
+            _, st = pond.step(cfg, a, b, stats=True)
+            total += st["mean_iters"]
+            nonconv += st["nonconverged"]
+            a, b = b, a
+        passes = {"mean_passes": total / steps, "nonconverged_node_steps": nonconv}
+    return ms, a, passes
+
+
+def cpu_baseline(cfg, state, sample_nodes, seed=0):
+    import oracle
+    f = state.f.double().cpu().numpy()
+    g = state.g.cpu().numpy()
+    rng = np.random.default_rng(seed)
+    nodes = rng.choice(cfg.nx * cfg.ny, size=sample_nodes, replace=False)
+    oc = oracle.OracleConfig(q=4, isothermal=cfg.isothermal, bc_x=cfg.bc_x, bc_y=cfg.bc_y,
+                             max_iter=cfg.max_iter, tau=cfg.tau, eps_abs=cfg.eps_abs,
+                             eps_rel=cfg.eps_rel)
+    t = time.perf_counter()
+    _, _, it, _ = oracle.step_nodes(f, g, oc, nodes)
+    dt = time.perf_counter() - t
+    return {"value": sample_nodes / dt / 1e6, "unit": "MLUPS", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"one step at {sample_nodes} random nodes of the FP64 state after the timed "
+                      f"run ({it.mean():.2f} passes/node), {dt:.1f} s"}
+
+
+def field_errors(cfg64, s64, cfg32, s32):
+    m64 = [t.cpu().numpy() for t in pond.moments(cfg64, s64)]
+    m32 = [t.cpu().numpy() for t in pond.moments(cfg32, s32)]
+    out = {}
+    for name, a, b, sc in zip(("rho", "ux", "uy", "T"), m32, m64, (None, 1.0, 1.0, None)):
+        scale = float(np.max(np.abs(b))) if sc is None else max(sc, float(np.max(np.abs(b))))
+        out[name] = {"max_rel": float(np.max(np.abs(a - b)) / scale),
+                     "mean_rel": float(np.mean(np.abs(a - b)) / scale)}
+    return out
+
+
+def main():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=2000)
+    p.add_argument("--warmup", type=int, default=10)
+    p.add_argument("--size", type=int, default=1024)
+    p.add_argument("--no-fp32", action="store_true")
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--cpu-sample", type=int, default=150000)
+    p.add_argument("--no-pass-count", action="store_true")
+    args = p.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the PonD step here has no multi-GPU path "
+              "(halo exchange is a design note, not built); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+
+    w = workloads.riemann2d(args.size, seed=3)
+    nodes = args.size * args.size
+    cfg64 = make_cfg(w, pond.POND_F64)
+    log(f"[bench] FP64 {args.size}^2, warmup {args.warmup}, steps {args.steps}")
+    ms64, s64, passes64 = run_steps(cfg64, w, args.steps, args.warmup,
+                                    count_passes=not args.no_pass_count)
+    mlups64 = nodes * args.steps / (ms64 * 1e-3) / 1e6
+    log(f"[bench] FP64 {ms64 / args.steps:.3f} ms/step, {mlups64:.1f} MLUPS, passes {passes64}")
+
+    result = {
+        "metric": "PonD MLUPS (D2Q16, 1024^2) FP32 vs FP64 at stated error; adjoint/forward ratio",
+        "value": mlups64,
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms64 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"riemann2d four-quadrant 2-D Riemann problem, D2Q16, "
+                               f"{args.size}x{args.size}, zero-gradient edges, tau 0.55, seed 3, "
+                               f"adaptive PC (App. E tolerances 1e-12/1e-10, cap 20), "
+                               f"{args.steps} steps from the initial state",
+                   "nx": args.size, "ny": args.size, "parallelism": "single GPU"},
+    }
+    if passes64:
+        node_passes = passes64["mean_passes"] * nodes
+        flops = FLOPS_PER_NODE_PASS * node_passes + FLOPS_PER_NODE_STEP * nodes
+        achieved = flops / (ms64 / args.steps * 1e-3) / 1e12
+        result["mean_pc_passes"] = passes64["mean_passes"]
+        result["nonconverged_node_steps"] = passes64["nonconverged_node_steps"]
+        result["roofline"] = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
+                              "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
+                              "traffic": None, "kernel": "k_step<4,double>",
+                              "flops_per_node_pass": FLOPS_PER_NODE_PASS}
+
+    if not args.no_fp32:
+        cfg32 = make_cfg(w, pond.POND_F32_MIXED)
+        log("[bench] FP32-mixed")
+        ms32, s32, passes32 = run_steps(cfg32, w, args.steps, args.warmup,
+                                        count_passes=not args.no_pass_count)
+        mlups32 = nodes * args.steps / (ms32 * 1e-3) / 1e6
+        log(f"[bench] FP32 {ms32 / args.steps:.3f} ms/step, {mlups32:.1f} MLUPS")
+        fp32 = {"value": mlups32, "unit": "MLUPS", "ms_per_step": ms32 / args.steps,
+                "speedup_vs_fp64": mlups32 / mlups64,
+                "error_vs_fp64_at_last_step": field_errors(cfg64, s64, cfg32, s32),
+                "tolerances": {"eps_abs": cfg32.eps_abs, "eps_rel": cfg32.eps_rel}}
+        if passes32:
+            fp32["mean_pc_passes"] = passes32["mean_passes"]
+            node_passes = passes32["mean_passes"] * nodes
+            flops = FLOPS_PER_NODE_PASS * node_passes + FLOPS_PER_NODE_STEP * nodes
+            a32 = flops / (ms32 / args.steps * 1e-3) / 1e12
+            fp32["roofline"] = {"bound": "alu", "achieved": a32, "peak": PEAK_FP32_TFLOPS,
+                                "unit": "TFLOP/s", "frac": a32 / PEAK_FP32_TFLOPS}
+        result["fp32_mixed"] = fp32
+
+    if not args.no_cpu_baseline:
+        log("[bench] oracle on host cores")
+        result["cpu_baseline"] = cpu_baseline(cfg64, s64, args.cpu_sample)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

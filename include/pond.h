@@ -1,0 +1,142 @@
+/*
+ * libpond -- C ABI of the Particles-on-Demand (PonD) time step on AMD gfx950.
+ *
+ * The method is that of Dorschner, Boesch and Karlin, "Particles-on-Demand for
+ * Kinetic Theory" (arXiv:1806.05089).  The state of the solver is, at every
+ * node of an equidistant periodic or bounded 2-D mesh (dx = dt = 1, App. C and
+ * the statement that dt = 1 is used throughout), the Q populations expressed in
+ * the node's own gauge lambda = {u, T} together with that gauge (main text,
+ * definition of f^lambda and of the limit gauge, eqs. (13)-(16)).
+ *
+ * Speed sets are tensor products of q one-dimensional speeds: q = 4 (D2Q16,
+ * roots of the probabilists' Hermite polynomial He_4, T_L = 1) or q = 3 (D2Q9
+ * of App. A, T_L = 1/3).  Population p = i*q + j carries the speed (c_i, c_j).
+ *
+ * Conventions shared by every call:
+ *   - All array arguments are DEVICE pointers owned by the caller, laid out as
+ *     structure-of-arrays planes, row-major [ny][nx] (x fastest).
+ *   - Every call is asynchronous on the given hipStream_t (passed as void*;
+ *     NULL = the default stream) unless stated otherwise.
+ *   - Return value: POND_OK (0) on success, a negative POND_E_* code otherwise;
+ *     pond_last_error() then returns a message (thread-local).  A failed
+ *     argument check launches nothing.
+ *   - Physical failures inside a step (no convergence, T <= 0, rho <= 0,
+ *     non-finite values) are not errors: they are counted in pond_stats and
+ *     marked in the per-node iteration plane.
+ */
+#ifndef POND_H_
+#define POND_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  POND_OK = 0,
+  POND_E_INVALID = -1,     /* a configuration value is out of range           */
+  POND_E_NULL = -2,        /* a required pointer is NULL                      */
+  POND_E_ALIAS = -3,       /* input and output buffers overlap                */
+  POND_E_STATE = -4,       /* pond_init found rho <= 0, T <= 0 or non-finite  */
+  POND_E_HIP = -5,         /* a HIP runtime call failed                       */
+  POND_E_UNSUPPORTED = -6  /* valid request that this build does not provide  */
+};
+
+enum { POND_F64 = 0, POND_F32_MIXED = 1 };
+enum { POND_PERIODIC = 0, POND_ZERO_GRADIENT = 1 };
+
+/* Bits of the per-node iteration plane written by pond_step. */
+#define POND_ITERS_MASK 0x3F        /* predictor-corrector passes, 1..63        */
+#define POND_ITERS_NONCONVERGED 0x40 /* the pass cap was hit before App. E's test */
+#define POND_ITERS_BAD 0x80          /* rho <= 0, T <= 0 or non-finite: output NaN */
+
+typedef struct {
+  int32_t nx, ny;     /* nodes per axis, >= 1                                   */
+  int32_t q1d;        /* 4: D2Q16; 3: D2Q9 (App. A)                             */
+  int32_t precision;  /* POND_F64: f in double; POND_F32_MIXED: f in float      */
+  int32_t isothermal; /* 1: T frozen at the node's stored value, eq. (12) dropped */
+  int32_t bc_x, bc_y; /* POND_PERIODIC or POND_ZERO_GRADIENT (stencil index clamp) */
+  int32_t max_iter;   /* cap on predictor-corrector passes, 1..63 (adaptive mode) */
+  int32_t fixed_iter; /* 0: adaptive (App. E test); n > 0: exactly n passes       */
+  int32_t seed_mode;  /* seed gauge: 0 own gauge at t - dt (eqs. (7)-(8));
+                         1 {0, T_L}; 2 {-u, T} (the seed-independence experiment) */
+  double tau;         /* BGK: 2 beta = 1 / tau, eq. (18); nu = T (tau - 1/2) dt    */
+  double eps_abs;     /* App. E tolerances (paper: 1e-12, 1e-10 in FP64)          */
+  double eps_rel;
+} pond_config;
+
+typedef struct {
+  void* f;        /* [q*q][ny][nx] populations in the node's own gauge:
+                     double for POND_F64, float for POND_F32_MIXED            */
+  double* g;      /* [3][ny][nx] gauge per node: u_x, u_y, T (double always)   */
+  uint8_t* iters; /* [ny][nx] written by pond_step (POND_ITERS_* bits); nullable */
+} pond_state;
+
+typedef struct {
+  int64_t nonconverged; /* nodes that hit max_iter in the last step             */
+  int64_t bad_state;    /* nodes with rho <= 0, T <= 0 or non-finite values      */
+  int32_t max_iters;    /* largest pass count over the grid in the last step     */
+  double mean_iters;    /* mean pass count per node in the last step             */
+} pond_stats;
+
+/*
+ * Equilibrium initial state (the paper leaves it open; eq. (17) gives the
+ * equilibrium of the co-moving gauge): f_p = rho W_i W_j in the gauge
+ * {u(x), T(x)}, g = (u_x, u_y, T).
+ * rho, ux, uy, T: [ny][nx] double device arrays.  out->f, out->g required;
+ * out->iters, if given, is set to 0.
+ * Checks every node on the device and returns POND_E_STATE if rho <= 0, T <= 0
+ * or a value is non-finite; this check synchronises the stream.
+ */
+int pond_init(const pond_config* cfg, const double* rho, const double* ux, const double* uy,
+              const double* T, pond_state* out, void* hip_stream);
+
+/*
+ * nsteps >= 1 PonD time steps (propagation with the predictor-corrector gauge
+ * iteration, eqs. (6)-(16) and App. E, then BGK collision, eqs. (17)-(18)).
+ * `in` is the state at t - dt, `out` receives the state after nsteps steps.
+ * in->f/g and out->f/g must not overlap (the semi-Lagrangian gather reads the
+ * whole field at t - dt).  For nsteps > 1 the call ping-pongs between the two
+ * buffers, so `in` is overwritten; with nsteps == 1 it is left intact.
+ * out->iters (nullable) receives the pass count and status bits of the last step.
+ * stats (HOST pointer, nullable): if given, filled for the last step; the call
+ * then synchronises the stream before returning.
+ */
+int pond_step(const pond_config* cfg, const pond_state* in, pond_state* out, int32_t nsteps,
+              void* hip_stream, pond_stats* stats);
+
+/*
+ * Macroscopic fields of a state: rho = sum f, rho u = sum v f, 2 rho T + rho|u|^2
+ * = sum |v|^2 f with v = sqrt(T_g / T_L) c + u_g of the node's own gauge g
+ * (eqs. (10)-(12)).  Mmn (nullable): the raw moments of eq. (2),
+ * [m*q + n][ny][nx] for m, n < q.  Every output pointer is nullable.
+ */
+int pond_moments(const pond_config* cfg, const pond_state* state, double* rho, double* ux,
+                 double* uy, double* T, double* Mmn, void* hip_stream);
+
+/*
+ * Vector-Jacobian product of one pond_step (nsteps = 1) about the forward pass
+ * in -> out_fwd.  out_fwd->iters must hold the pass counts written by that
+ * forward step (the adjoint differentiates the computed map with these counts
+ * fixed, i.e. the unrolled predictor-corrector iteration).
+ * adj_out: cotangents of (f, g) at t (adj_out->f is double in both precisions).
+ * adj_in:  receives the cotangents of (f, g) at t - dt (double); it is
+ *          overwritten, not accumulated.  Must not overlap the other buffers.
+ * adj_tau (device double*, nullable): d/dtau of <adj_out, out> is ADDED to it.
+ */
+int pond_step_adjoint(const pond_config* cfg, const pond_state* in, const pond_state* out_fwd,
+                      const pond_state* adj_out, pond_state* adj_in, double* adj_tau,
+                      void* hip_stream);
+
+/* Message for the last nonzero return on this thread ("" if none). */
+const char* pond_last_error(void);
+
+/* ABI version of this header (major * 100 + minor). */
+int pond_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* POND_H_ */

@@ -1,0 +1,225 @@
+// C ABI of libpond: argument checks, buffer ping-pong and kernel launches.
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+
+#include "pond.h"
+#include "pond_internal.hpp"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* where) {
+  return fail(POND_E_HIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+// Small per-device buffer for step counters, allocated on first use and held
+// until the process ends.
+constexpr int kMaxDevices = 64;
+std::mutex g_mutex;
+pond::StepCounters* g_counters[kMaxDevices] = {nullptr};
+
+int counters_for_current_device(pond::StepCounters** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices) return fail(POND_E_UNSUPPORTED, "device index too large");
+  std::lock_guard<std::mutex> lock(g_mutex);
+  if (!g_counters[dev]) {
+    e = hipMalloc(reinterpret_cast<void**>(&g_counters[dev]), sizeof(pond::StepCounters));
+    if (e != hipSuccess) {
+      g_counters[dev] = nullptr;
+      return hip_fail(e, "hipMalloc(counters)");
+    }
+  }
+  *out = g_counters[dev];
+  return POND_OK;
+}
+
+size_t f_bytes(const pond_config& c) {
+  const size_t plane = (size_t)c.nx * c.ny;
+  return plane * c.q1d * c.q1d * (c.precision == POND_F64 ? sizeof(double) : sizeof(float));
+}
+size_t g_bytes(const pond_config& c) { return (size_t)c.nx * c.ny * 3 * sizeof(double); }
+
+bool overlap(const void* a, size_t na, const void* b, size_t nb) {
+  const char* pa = static_cast<const char*>(a);
+  const char* pb = static_cast<const char*>(b);
+  return pa < pb + nb && pb < pa + na;
+}
+
+int check_config(const pond_config* c) {
+  if (!c) return fail(POND_E_NULL, "config is NULL");
+  if (c->nx < 1 || c->ny < 1) return fail(POND_E_INVALID, "nx and ny must be >= 1");
+  if ((long long)c->nx * c->ny > (1ll << 31))
+    return fail(POND_E_INVALID, "grid larger than 2^31 nodes");
+  if (c->q1d != 3 && c->q1d != 4) return fail(POND_E_INVALID, "q1d must be 3 (D2Q9) or 4 (D2Q16)");
+  if (c->precision != POND_F64 && c->precision != POND_F32_MIXED)
+    return fail(POND_E_INVALID, "precision must be POND_F64 or POND_F32_MIXED");
+  if (c->isothermal != 0 && c->isothermal != 1) return fail(POND_E_INVALID, "isothermal must be 0 or 1");
+  if ((c->bc_x != POND_PERIODIC && c->bc_x != POND_ZERO_GRADIENT) ||
+      (c->bc_y != POND_PERIODIC && c->bc_y != POND_ZERO_GRADIENT))
+    return fail(POND_E_INVALID, "bc must be POND_PERIODIC or POND_ZERO_GRADIENT");
+  if (c->max_iter < 1 || c->max_iter > POND_ITERS_MASK)
+    return fail(POND_E_INVALID, "max_iter must be in 1..63");
+  if (c->fixed_iter < 0 || c->fixed_iter > POND_ITERS_MASK)
+    return fail(POND_E_INVALID, "fixed_iter must be in 0..63");
+  if (c->seed_mode < 0 || c->seed_mode > 2) return fail(POND_E_INVALID, "seed_mode must be 0, 1 or 2");
+  if (!(c->tau > 0.0) || !(c->tau < 1e30)) return fail(POND_E_INVALID, "tau must be finite and > 0");
+  if (!(c->eps_abs >= 0.0) || !(c->eps_rel >= 0.0))
+    return fail(POND_E_INVALID, "eps_abs and eps_rel must be >= 0");
+  return POND_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* pond_last_error(void) { return g_last_error.c_str(); }
+
+int pond_abi_version(void) { return 100; }
+
+int pond_init(const pond_config* cfg, const double* rho, const double* ux, const double* uy,
+              const double* T, pond_state* out, void* hip_stream) {
+  g_last_error.clear();
+  int rc = check_config(cfg);
+  if (rc) return rc;
+  if (!rho || !ux || !uy || !T) return fail(POND_E_NULL, "pond_init: a field pointer is NULL");
+  if (!out || !out->f || !out->g) return fail(POND_E_NULL, "pond_init: output state is NULL");
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  pond::StepCounters* cnt = nullptr;
+  if ((rc = counters_for_current_device(&cnt))) return rc;
+  hipError_t e = pond::launch_zero_u64(&cnt->bad, 1, s);
+  if (e != hipSuccess) return hip_fail(e, "pond_init zero");
+  e = pond::launch_init(*cfg, rho, ux, uy, T, out->f, out->g, out->iters, &cnt->bad, s);
+  if (e != hipSuccess) return hip_fail(e, "pond_init launch");
+  unsigned long long bad = 0;
+  e = hipMemcpyAsync(&bad, &cnt->bad, sizeof(bad), hipMemcpyDeviceToHost, s);
+  if (e != hipSuccess) return hip_fail(e, "pond_init copy");
+  e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "pond_init sync");
+  if (bad) {
+    char buf[128];
+    snprintf(buf, sizeof(buf), "pond_init: %llu nodes with rho <= 0, T <= 0 or non-finite values", bad);
+    return fail(POND_E_STATE, buf);
+  }
+  return POND_OK;
+}
+
+int pond_step(const pond_config* cfg, const pond_state* in, pond_state* out, int32_t nsteps,
+              void* hip_stream, pond_stats* stats) {
+  g_last_error.clear();
+  int rc = check_config(cfg);
+  if (rc) return rc;
+  if (!in || !out || !in->f || !in->g || !out->f || !out->g)
+    return fail(POND_E_NULL, "pond_step: a state buffer is NULL");
+  if (nsteps < 1) return fail(POND_E_INVALID, "pond_step: nsteps must be >= 1");
+  const size_t fb = f_bytes(*cfg), gb = g_bytes(*cfg);
+  if (overlap(in->f, fb, out->f, fb) || overlap(in->g, gb, out->g, gb) ||
+      overlap(in->f, fb, out->g, gb) || overlap(in->g, gb, out->f, fb))
+    return fail(POND_E_ALIAS, "pond_step: input and output state overlap");
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  pond::StepCounters* cnt = nullptr;
+  if (stats && (rc = counters_for_current_device(&cnt))) return rc;
+
+  pond::StepArgs a;
+  a.nx = cfg->nx;
+  a.ny = cfg->ny;
+  a.bc_x = cfg->bc_x;
+  a.bc_y = cfg->bc_y;
+  a.max_iter = cfg->max_iter;
+  a.fixed_iter = cfg->fixed_iter;
+  a.seed_mode = cfg->seed_mode;
+  a.isothermal = cfg->isothermal;
+  a.tau = cfg->tau;
+  a.eps_abs = cfg->eps_abs;
+  a.eps_rel = cfg->eps_rel;
+  a.iters = out->iters;
+
+  const void* src_f = in->f;
+  const double* src_g = in->g;
+  hipError_t e;
+  for (int k = 0; k < nsteps; ++k) {
+    const bool to_out = (k % 2 == 0);
+    void* dst_f = to_out ? out->f : in->f;
+    double* dst_g = to_out ? out->g : in->g;
+    const bool last = (k == nsteps - 1);
+    a.f_in = src_f;
+    a.g_in = src_g;
+    a.f_out = dst_f;
+    a.g_out = dst_g;
+    a.counters = (last && cnt) ? cnt : nullptr;
+    if (a.counters) {
+      e = pond::launch_zero_u64(reinterpret_cast<unsigned long long*>(cnt), 4, s);
+      if (e != hipSuccess) return hip_fail(e, "pond_step zero counters");
+    }
+    e = pond::launch_step(*cfg, a, s);
+    if (e != hipSuccess) return hip_fail(e, "pond_step launch");
+    src_f = dst_f;
+    src_g = dst_g;
+  }
+  if (nsteps % 2 == 0) {
+    // The last step wrote `in`; move the result to `out`.
+    e = hipMemcpyAsync(out->f, in->f, fb, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(out->g, in->g, gb, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "pond_step final copy");
+  }
+  if (stats) {
+    pond::StepCounters h;
+    e = hipMemcpyAsync(&h, cnt, sizeof(h), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "pond_step stats");
+    stats->nonconverged = (int64_t)h.nonconverged;
+    stats->bad_state = (int64_t)h.bad;
+    stats->max_iters = (int32_t)h.max_passes;
+    stats->mean_iters = (double)h.sum_passes / ((double)cfg->nx * cfg->ny);
+  }
+  return POND_OK;
+}
+
+int pond_moments(const pond_config* cfg, const pond_state* state, double* rho, double* ux,
+                 double* uy, double* T, double* Mmn, void* hip_stream) {
+  g_last_error.clear();
+  int rc = check_config(cfg);
+  if (rc) return rc;
+  if (!state || !state->f || !state->g) return fail(POND_E_NULL, "pond_moments: state is NULL");
+  hipError_t e = pond::launch_moments(*cfg, state->f, state->g, rho, ux, uy, T, Mmn,
+                                      static_cast<hipStream_t>(hip_stream));
+  if (e != hipSuccess) return hip_fail(e, "pond_moments launch");
+  return POND_OK;
+}
+
+int pond_step_adjoint(const pond_config* cfg, const pond_state* in, const pond_state* out_fwd,
+                      const pond_state* adj_out, pond_state* adj_in, double* adj_tau,
+                      void* hip_stream) {
+  g_last_error.clear();
+  int rc = check_config(cfg);
+  if (rc) return rc;
+  if (!in || !out_fwd || !adj_out || !adj_in || !in->f || !in->g || !out_fwd->iters ||
+      !adj_out->f || !adj_out->g || !adj_in->f || !adj_in->g)
+    return fail(POND_E_NULL, "pond_step_adjoint: a required buffer is NULL");
+  const size_t plane = (size_t)cfg->nx * cfg->ny;
+  const size_t afb = plane * cfg->q1d * cfg->q1d * sizeof(double), agb = g_bytes(*cfg);
+  const size_t fb = f_bytes(*cfg);
+  if (overlap(adj_in->f, afb, adj_out->f, afb) || overlap(adj_in->g, agb, adj_out->g, agb) ||
+      overlap(adj_in->f, afb, in->f, fb) || overlap(adj_in->g, agb, in->g, agb) ||
+      overlap(adj_in->f, afb, adj_in->g, agb))
+    return fail(POND_E_ALIAS, "pond_step_adjoint: adj_in overlaps another buffer");
+  hipError_t e = pond::launch_adjoint(*cfg, in->f, in->g, out_fwd->iters, (const double*)adj_out->f,
+                                      adj_out->g, (double*)adj_in->f, adj_in->g, adj_tau,
+                                      static_cast<hipStream_t>(hip_stream));
+  if (e == hipErrorNotSupported) return fail(POND_E_UNSUPPORTED, "pond_step_adjoint: not available");
+  if (e != hipSuccess) return hip_fail(e, "pond_step_adjoint launch");
+  return POND_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,154 @@
+// Device-side building blocks of the PonD step for gfx950: speed sets,
+// third-order Lagrange interpolation weights and the per-axis transfer rows.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pond {
+
+// ------------------------------------------------------------ speed sets
+// D2Q16: per-axis speeds are the roots of the probabilists' Hermite
+// polynomial He_4, +-sqrt(3 -+ sqrt 6), with Gauss-Hermite weights
+// (3 +- sqrt 6)/12 (the larger weight on the inner speed); T_L = 1.
+// D2Q9 (App. A): speeds -1, 0, 1 with weights 1/6, 2/3, 1/6; T_L = 1/3.
+template <int Q1> struct Lat;
+
+template <> struct Lat<4> {
+  static constexpr double TL = 1.0;
+  static constexpr double inv_TL = 1.0;
+  __host__ __device__ static constexpr double c(int i) {
+    return i == 0 ? -2.334414218338977239317512
+         : i == 1 ? -0.7419637843027258576485136
+         : i == 2 ? 0.7419637843027258576485136
+                  : 2.334414218338977239317512;
+  }
+  __host__ __device__ static constexpr double w(int i) {
+    return (i == 0 || i == 3) ? 0.04587585476806849181689299 : 0.454124145231931508183107;
+  }
+};
+
+template <> struct Lat<3> {
+  static constexpr double TL = 1.0 / 3.0;
+  static constexpr double inv_TL = 3.0;
+  __host__ __device__ static constexpr double c(int i) { return double(i - 1); }
+  __host__ __device__ static constexpr double w(int i) { return i == 1 ? 2.0 / 3.0 : 1.0 / 6.0; }
+};
+
+// 1 / prod_{m != k} (c_k - c_m): normalisation of the Lagrange basis
+// polynomial attached to speed k.
+template <int Q1>
+__host__ __device__ constexpr double lag_inv_den(int k) {
+  double d = 1.0;
+  for (int m = 0; m < Q1; ++m)
+    if (m != k) d *= (Lat<Q1>::c(k) - Lat<Q1>::c(m));
+  return 1.0 / d;
+}
+
+// prod_{m != k} (z - c_m): unnormalised Lagrange basis polynomial of speed k.
+template <int Q1, class R>
+__device__ __forceinline__ R lag_num(int k, R z) {
+  R p = R(1);
+#pragma unroll
+  for (int m = 0; m < Q1; ++m)
+    if (m != k) p *= (z - R(Lat<Q1>::c(m)));
+  return p;
+}
+
+// Monomial coefficients of the normalised Lagrange basis polynomial of speed
+// k: l_k(z) = sum_e coef[e] z^e (for Horner evaluation with a run-time k).
+template <int Q1>
+struct LagCoef {
+  double v[4][4];
+  constexpr LagCoef() : v{} {
+    for (int k = 0; k < Q1; ++k) {
+      double p[4] = {1.0, 0.0, 0.0, 0.0};  // running product, degree <= 3
+      int deg = 0;
+      for (int m = 0; m < Q1; ++m) {
+        if (m == k) continue;
+        // p(z) *= (z - c_m)
+        for (int e = deg + 1; e >= 1; --e) p[e] = p[e - 1] - Lat<Q1>::c(m) * p[e];
+        p[0] = -Lat<Q1>::c(m) * p[0];
+        ++deg;
+      }
+      const double s = lag_inv_den<Q1>(k);
+      for (int e = 0; e < 4; ++e) v[k][e] = p[e] * s;
+    }
+  }
+};
+
+// l_k(z) for a run-time k that is uniform across the wave.
+template <int Q1>
+__device__ __forceinline__ double lag_eval(int k, double z) {
+  constexpr LagCoef<Q1> C{};
+  double c0, c1, c2, c3;
+  // uniform selects (k is the same in every lane)
+  c0 = C.v[0][0]; c1 = C.v[0][1]; c2 = C.v[0][2]; c3 = C.v[0][3];
+#pragma unroll
+  for (int kk = 1; kk < Q1; ++kk) {
+    if (k == kk) { c0 = C.v[kk][0]; c1 = C.v[kk][1]; c2 = C.v[kk][2]; c3 = C.v[kk][3]; }
+  }
+  return ((c3 * z + c2) * z + c1) * z + c0;
+}
+
+// ------------------------------------------------ transfer rows (eq. 4)
+// Matching the q per-axis moments of eq. (2) between a source gauge
+// {u_s, theta_s} and a target gauge {u_t, theta_t} is Lagrange interpolation
+// on the target speeds: the transfer factor is
+//     G[k][i] = l_k(z_i),   z_i = r c_i + d,
+//     r = sqrt(theta_s / theta_t),  d = (u_s - u_t) / sqrt(theta_t),
+// with l_k the Lagrange basis polynomial of speed c_k (App. B gives the same
+// matrix for D2Q9 in closed form).  Row k for all source speeds i:
+template <int Q1>
+__device__ __forceinline__ void transfer_row(int k, double r, double d, double* row) {
+#pragma unroll
+  for (int i = 0; i < Q1; ++i) row[i] = lag_num<Q1>(k, r * Lat<Q1>::c(i) + d) * lag_inv_den<Q1>(k);
+}
+
+// Row k of the transfer factor for a run-time (wave-uniform) k.
+template <int Q1>
+__device__ __forceinline__ void transfer_row_rt(int k, double r, double d, double* row) {
+#pragma unroll
+  for (int i = 0; i < Q1; ++i) row[i] = lag_eval<Q1>(k, r * Lat<Q1>::c(i) + d);
+}
+
+// Speed c_i for a run-time (wave-uniform) i.
+template <int Q1>
+__device__ __forceinline__ double speed_rt(int i) {
+  double c = Lat<Q1>::c(0);
+#pragma unroll
+  for (int k = 1; k < Q1; ++k)
+    if (i == k) c = Lat<Q1>::c(k);
+  return c;
+}
+
+// ----------------------------------------------- reconstruction (App. C)
+// Third-order Lagrange weights on the four collocation points x0 + n,
+// x0 = floor(x) - 1, at local coordinate t = x - x0 in [1, 2).
+__device__ __forceinline__ void interp_weights(double t, double* a) {
+  const double t0 = t, t1 = t - 1.0, t2 = t - 2.0, t3 = t - 3.0;
+  a[0] = t1 * t2 * t3 * (-1.0 / 6.0);
+  a[1] = t0 * t2 * t3 * 0.5;
+  a[2] = t0 * t1 * t3 * (-0.5);
+  a[3] = t0 * t1 * t2 * (1.0 / 6.0);
+}
+
+// Stencil index -> node index: periodic wrap or zero-gradient clamp.
+__device__ __forceinline__ int wrap_index(int i, int n, int bc) {
+  if (bc == 0) {
+    int r = i % n;
+    return r < 0 ? r + n : r;
+  }
+  return i < 0 ? 0 : (i >= n ? n - 1 : i);
+}
+
+// Error-free sum (Knuth TwoSum) for compensated accumulation.
+template <class R>
+__device__ __forceinline__ void two_sum_acc(R& s, R& c, R x) {
+  const R t = s + x;
+  const R bp = t - s;
+  c += (s - (t - bp)) + (x - bp);
+  s = t;
+}
+
+}  // namespace pond

@@ -1,0 +1,216 @@
+"""HIP path vs the CPU oracle, element by element, on seeded synthetic inputs.
+
+Bar: FP64 path within 1e-12 (relative to the field's scale) of the oracle in
+fixed-iteration mode; adaptive mode within 1e-9 with matching pass counts away
+from the App. E threshold; FP32-mixed path within the per-field tolerances
+stated in the tests.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1806_05089_amd import pond, workloads
+from tests.parity import rel_err, state_errors
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+
+
+def _cfg(w, q=4, **kw):
+    ny, nx = w.shape
+    base = dict(nx=nx, ny=ny, q1d=q, isothermal=w.isothermal, bc_x=w.bc_x, bc_y=w.bc_y,
+                tau=w.tau)
+    base.update(kw)
+    return pond.PondConfig(**base)
+
+
+def _ocfg(c: pond.PondConfig):
+    return oracle.OracleConfig(q=c.q1d, isothermal=c.isothermal, bc_x=c.bc_x, bc_y=c.bc_y,
+                               max_iter=c.max_iter, fixed_iter=c.fixed_iter,
+                               seed_mode=c.seed_mode, tau=c.tau, eps_abs=c.eps_abs,
+                               eps_rel=c.eps_rel)
+
+
+def _run_both(w, cfg, nsteps=1):
+    """Same initial fields through both sides; returns (gpu f,g,iters), (oracle f,g,iters)."""
+    st = pond.init(cfg, w.rho, w.ux, w.uy, w.T)
+    out, _ = pond.step(cfg, st, nsteps=nsteps)
+    torch.cuda.synchronize()
+    f0, g0 = oracle.init(w.rho, w.ux, w.uy, w.T, q=cfg.q1d)
+    oc = _ocfg(cfg)
+    for _ in range(nsteps):
+        f0, g0, it, stt = oracle.step(f0, g0, oc)
+    gpu = (out.f.double().cpu().numpy(), out.g.cpu().numpy(), out.iters.cpu().numpy())
+    return gpu, (f0, g0, it, stt)
+
+
+def _u_scale(w):
+    return max(1e-3, float(np.max(np.hypot(w.ux, w.uy))))
+
+
+CASES_FIXED = [
+    # name, workload factory, q, fixed passes
+    ("smooth_thermal_48x40", lambda: workloads.random_smooth(48, 40, seed=1), 4, 3),
+    ("tgv32_isothermal", lambda: workloads.taylor_green(32), 4, 2),
+    ("sod_96x3_zero_gradient", lambda: workloads.sod(96, 3), 4, 3),
+    ("mach5_24x20", lambda: workloads.mach5(24, seed=0), 4, 2),
+    ("ragged_67x5", lambda: workloads.random_smooth(67, 5, seed=2, mach=0.6), 4, 3),
+    ("d2q9_smooth_40x36", lambda: workloads.random_smooth(40, 36, seed=3, T0=1.0 / 3.0, mach=0.2), 3, 3),
+]
+
+
+@pytest.mark.parametrize("name,make,q,npass", CASES_FIXED, ids=[c[0] for c in CASES_FIXED])
+def test_step_fp64_fixed_iter(gpu, name, make, q, npass):
+    print(f"case {name}", flush=True)
+    w = make()
+    cfg = _cfg(w, q=q, fixed_iter=npass)
+    (fg, gg, ig), (fo, go, io, so) = _run_both(w, cfg)
+    errs = state_errors(fg, gg, fo, go, u_scale=_u_scale(w), T_scale=float(np.max(w.T)))
+    assert max(errs.values()) < TOL64, errs
+    assert np.all((ig & pond.POND_ITERS_MASK) == npass)
+
+
+CASES_ADAPTIVE = [
+    ("smooth_thermal_48x40", lambda: workloads.random_smooth(48, 40, seed=4), 4),
+    ("tgv32_isothermal", lambda: workloads.taylor_green(32), 4),
+    ("sod_128x2", lambda: workloads.sod(128, 2), 4),
+    ("d2q9_smooth", lambda: workloads.random_smooth(40, 36, seed=5, T0=1.0 / 3.0, mach=0.2), 3),
+]
+
+
+@pytest.mark.parametrize("name,make,q", CASES_ADAPTIVE, ids=[c[0] for c in CASES_ADAPTIVE])
+def test_step_fp64_adaptive(gpu, name, make, q):
+    print(f"case {name}", flush=True)
+    w = make()
+    cfg = _cfg(w, q=q, max_iter=20)
+    (fg, gg, ig), (fo, go, io, so) = _run_both(w, cfg)
+    same = (ig & pond.POND_ITERS_MASK) == io
+    assert same.mean() > 0.98, same.mean()
+    errs = state_errors(fg, gg, fo, go, u_scale=_u_scale(w), T_scale=float(np.max(w.T)))
+    # nodes that stopped one pass apart differ by about the App. E tolerance
+    assert max(errs.values()) < 1e-9, errs
+    if same.all():
+        assert max(errs.values()) < TOL64, errs
+
+
+@pytest.mark.parametrize("nsteps", [1, 2, 5])
+def test_multi_step_pingpong(gpu, nsteps):
+    w = workloads.taylor_green(24, mach=0.1)
+    cfg = _cfg(w, fixed_iter=2)
+    (fg, gg, _), (fo, go, _, _) = _run_both(w, cfg, nsteps=nsteps)
+    errs = state_errors(fg, gg, fo, go, u_scale=0.1)
+    assert max(errs.values()) < TOL64, errs
+
+
+def test_init_and_moments(gpu):
+    w = workloads.random_smooth(33, 17, seed=7, mach=1.5)
+    for q, prec in ((4, pond.POND_F64), (3, pond.POND_F64), (4, pond.POND_F32_MIXED)):
+        cfg = _cfg(w, q=q, precision=prec)
+        T = w.T if q == 4 else w.T / 3.0
+        st = pond.init(cfg, w.rho, w.ux, w.uy, T)
+        rho, ux, uy, Tm, M = (a.cpu().numpy() for a in pond.moments(cfg, st, raw=True))
+        f0, g0 = oracle.init(w.rho, w.ux, w.uy, T, q=q)
+        ro, uxo, uyo, To, Mo = oracle.moments(f0, g0, q=q, with_raw=True)
+        tol = 1e-13 if prec == pond.POND_F64 else 2e-7
+        assert rel_err(st.f.double().cpu().numpy(), f0) < tol
+        assert np.array_equal(st.g.cpu().numpy(), g0)
+        assert rel_err(rho, ro) < tol
+        assert rel_err(ux, uxo, 1.0) < 10 * tol and rel_err(uy, uyo, 1.0) < 10 * tol
+        assert rel_err(Tm, To) < 10 * tol
+        assert rel_err(M, Mo) < 10 * tol
+
+
+def test_fp32_mixed_vs_oracle(gpu):
+    """FP32 bulk arithmetic, FP64 transfer rows and convergence test."""
+    w = workloads.random_smooth(48, 40, seed=8, mach=0.5)
+    cfg = _cfg(w, precision=pond.POND_F32_MIXED, fixed_iter=3)
+    (fg, gg, _), (fo, go, _, _) = _run_both(w, cfg)
+    errs = state_errors(fg, gg, fo, go, u_scale=_u_scale(w), T_scale=float(np.max(w.T)))
+    # single-step error of FP32 arithmetic (eps32 = 6e-8) through ~300 terms
+    assert errs["f"] < 2e-6 and errs["ux"] < 2e-6 and errs["uy"] < 2e-6 and errs["T"] < 2e-6, errs
+
+
+def test_edge_single_node_and_strips(gpu):
+    for nx, ny in ((1, 1), (1, 7), (9, 1), (2, 2)):
+        w = workloads.random_smooth(nx, ny, seed=nx * 10 + ny, mach=0.4)
+        cfg = _cfg(w, fixed_iter=2)
+        (fg, gg, _), (fo, go, _, _) = _run_both(w, cfg)
+        errs = state_errors(fg, gg, fo, go, u_scale=1.0, T_scale=1.0)
+        assert max(errs.values()) < TOL64, (nx, ny, errs)
+
+
+def test_zero_gradient_both_axes(gpu):
+    w = workloads.riemann2d(40, seed=3)
+    cfg = _cfg(w, fixed_iter=3)
+    (fg, gg, _), (fo, go, _, _) = _run_both(w, cfg)
+    errs = state_errors(fg, gg, fo, go, u_scale=_u_scale(w), T_scale=float(np.max(w.T)))
+    assert max(errs.values()) < TOL64, errs
+
+
+def test_seed_modes_match_oracle(gpu):
+    w = workloads.random_smooth(32, 32, seed=9, mach=0.2)
+    for mode in (1, 2):
+        cfg = _cfg(w, seed_mode=mode, max_iter=40)
+        (fg, gg, ig), (fo, go, io, so) = _run_both(w, cfg)
+        errs = state_errors(fg, gg, fo, go, u_scale=_u_scale(w), T_scale=float(np.max(w.T)))
+        assert max(errs.values()) < 1e-9, (mode, errs)
+
+
+def test_stats_and_bad_state(gpu):
+    w = workloads.random_smooth(40, 24, seed=11)
+    cfg = _cfg(w, max_iter=1)
+    st = pond.init(cfg, w.rho, w.ux, w.uy, w.T)
+    out, stats = pond.step(cfg, st, stats=True)
+    it = out.iters.cpu().numpy()
+    assert stats["max_iters"] == 1 and stats["bad_state"] == 0
+    assert stats["nonconverged"] == int(np.count_nonzero(it & pond.POND_ITERS_NONCONVERGED))
+    assert stats["nonconverged"] > 0
+    # a state with T <= 0 at one node (forced from the host): flagged, NaN output, no error
+    g = st.g.clone()
+    g[2, 5, 7] = -1.0
+    bad_in = pond.PondState(st.f.clone(), g, st.iters.clone())
+    cfg2 = _cfg(w, max_iter=20)
+    out2, stats2 = pond.step(cfg2, bad_in, stats=True)
+    it2 = out2.iters.cpu().numpy()
+    assert stats2["bad_state"] == int(np.count_nonzero(it2 & pond.POND_ITERS_BAD)) > 0
+    assert np.isnan(out2.g.cpu().numpy()[:, it2 & pond.POND_ITERS_BAD > 0]).all()
+
+
+def test_init_rejects_bad_fields(gpu):
+    w = workloads.uniform(8, 8)
+    cfg = _cfg(w)
+    T = w.T.copy()
+    T[3, 3] = 0.0
+    with pytest.raises(pond.PondError) as e:
+        pond.init(cfg, w.rho, w.ux, w.uy, T)
+    assert e.value.code == -4
+
+
+def test_full_size_sampled_riemann_1024(gpu):
+    """1024^2 four-quadrant Riemann input in the benchmark's launch configuration,
+    checked against the oracle at 384 sampled nodes (all quadrants, interfaces, edges)."""
+    w = workloads.riemann2d(1024, seed=3)
+    rng = np.random.default_rng(0)
+    for prec, tol in ((pond.POND_F64, TOL64), (pond.POND_F32_MIXED, 2e-6)):
+        cfg = _cfg(w, precision=prec, max_iter=20)
+        if prec == pond.POND_F32_MIXED:
+            cfg = cfg.replace(eps_abs=1e-6, eps_rel=1e-5, fixed_iter=3)
+        else:
+            cfg = cfg.replace(fixed_iter=3)
+        st = pond.init(cfg, w.rho, w.ux, w.uy, w.T)
+        out, _ = pond.step(cfg, st)
+        f_in = st.f.double().cpu().numpy()
+        g_in = st.g.cpu().numpy()
+        N = 1024
+        pts = list(rng.integers(0, N * N, 256))
+        for y in (0, 1, 511, 512, 1022, 1023):
+            for x in (0, 2, 510, 511, 512, 513, 1023):
+                pts.append(y * N + x)
+        pts = np.array(pts[:384], dtype=np.int64)
+        fo, go, io, so = oracle.step_nodes(f_in, g_in, _ocfg(cfg), pts)
+        fg = out.f.double().cpu().numpy().reshape(16, -1)[:, pts]
+        gg = out.g.cpu().numpy().reshape(3, -1)[:, pts]
+        errs = state_errors(fg, gg, fo, go, u_scale=1.0, T_scale=float(np.max(w.T)))
+        assert max(errs.values()) < tol, (prec, errs)
