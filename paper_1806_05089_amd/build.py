@@ -11,7 +11,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libpond.so")
-SOURCES = ["pond_api.hip", "pond_forward.hip", "pond_adjoint.hip"]
+SOURCES = ["pond_api.hip", "pond_forward.hip", "pond_step.hip", "pond_adjoint.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

@@ -77,18 +77,40 @@ struct LagCoef {
   }
 };
 
-// l_k(z) for a run-time k that is uniform across the wave.
+// Per-speed tables in constant memory for wave-uniform run-time indices:
+// the speed c_k and the Horner coefficients of l_k.
 template <int Q1>
-__device__ __forceinline__ double lag_eval(int k, double z) {
-  constexpr LagCoef<Q1> C{};
-  double c0, c1, c2, c3;
-  // uniform selects (k is the same in every lane)
-  c0 = C.v[0][0]; c1 = C.v[0][1]; c2 = C.v[0][2]; c3 = C.v[0][3];
-#pragma unroll
-  for (int kk = 1; kk < Q1; ++kk) {
-    if (k == kk) { c0 = C.v[kk][0]; c1 = C.v[kk][1]; c2 = C.v[kk][2]; c3 = C.v[kk][3]; }
+struct SpeedTable {
+  double c[4];
+  double lag[4][4];
+  constexpr SpeedTable() : c{}, lag{} {
+    constexpr LagCoef<Q1> C{};
+    for (int k = 0; k < Q1; ++k) {
+      c[k] = Lat<Q1>::c(k);
+      for (int e = 0; e < 4; ++e) lag[k][e] = C.v[k][e];
+    }
   }
-  return ((c3 * z + c2) * z + c1) * z + c0;
+};
+
+__constant__ const SpeedTable<4> kSpeeds4 = SpeedTable<4>();
+__constant__ const SpeedTable<3> kSpeeds3 = SpeedTable<3>();
+
+template <int Q1>
+__device__ __forceinline__ const SpeedTable<Q1>& speeds();
+template <>
+__device__ __forceinline__ const SpeedTable<4>& speeds<4>() { return kSpeeds4; }
+template <>
+__device__ __forceinline__ const SpeedTable<3>& speeds<3>() { return kSpeeds3; }
+
+// Horner coefficients of the Lagrange basis polynomial of a speed.
+struct LagRow {
+  double l0, l1, l2, l3;
+};
+
+template <int Q1>
+__device__ __forceinline__ LagRow lag_row(int k) {
+  const SpeedTable<Q1>& t = speeds<Q1>();
+  return LagRow{t.lag[k][0], t.lag[k][1], t.lag[k][2], t.lag[k][3]};
 }
 
 // ------------------------------------------------ transfer rows (eq. 4)
@@ -105,21 +127,20 @@ __device__ __forceinline__ void transfer_row(int k, double r, double d, double* 
   for (int i = 0; i < Q1; ++i) row[i] = lag_num<Q1>(k, r * Lat<Q1>::c(i) + d) * lag_inv_den<Q1>(k);
 }
 
-// Row k of the transfer factor for a run-time (wave-uniform) k.
+// Row of the transfer factor for the basis polynomial with coefficients P.
 template <int Q1>
-__device__ __forceinline__ void transfer_row_rt(int k, double r, double d, double* row) {
+__device__ __forceinline__ void transfer_row_coef(const LagRow& P, double r, double d, double* row) {
 #pragma unroll
-  for (int i = 0; i < Q1; ++i) row[i] = lag_eval<Q1>(k, r * Lat<Q1>::c(i) + d);
+  for (int i = 0; i < Q1; ++i) {
+    const double z = fma(r, Lat<Q1>::c(i), d);
+    row[i] = fma(fma(fma(P.l3, z, P.l2), z, P.l1), z, P.l0);
+  }
 }
 
 // Speed c_i for a run-time (wave-uniform) i.
 template <int Q1>
 __device__ __forceinline__ double speed_rt(int i) {
-  double c = Lat<Q1>::c(0);
-#pragma unroll
-  for (int k = 1; k < Q1; ++k)
-    if (i == k) c = Lat<Q1>::c(k);
-  return c;
+  return speeds<Q1>().c[i];
 }
 
 // ----------------------------------------------- reconstruction (App. C)
