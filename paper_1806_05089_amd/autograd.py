@@ -1,0 +1,106 @@
+"""Differentiable PonD rollouts: torch.autograd over the hand-written adjoint.
+
+``PondRollout.apply(f0, g0, tau, cfg, nsteps, checkpoint_every)`` runs
+``nsteps`` pond_step launches and returns the final (f, g).  Its backward pass
+replays each segment of ``checkpoint_every`` steps from the saved state at the
+segment start (so memory holds nsteps / K checkpoints plus one segment) and
+calls ``pond_step_adjoint`` step by step in reverse.  Gradients flow to the
+initial populations and gauge and to tau (nu = T_ref (tau - 1/2) dt, so
+dJ/dnu = (dJ/dtau) / T_ref).
+
+``equilibrium_state`` builds the initial state from macroscopic fields with
+the same kernel as pond_init and gives the fields their gradients; the
+equilibrium f = rho W_i W_j is linear in rho, so its transpose is a weighted
+sum over populations.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import pond
+from .pond import PondConfig, PondState
+
+
+def _weights(cfg: PondConfig, device) -> torch.Tensor:
+    """rho -> f map of the equilibrium initial state, read back from pond_init."""
+    one = torch.ones((1, 1), dtype=torch.float64)
+    zero = torch.zeros((1, 1), dtype=torch.float64)
+    c1 = cfg.replace(nx=1, ny=1, precision=pond.POND_F64)
+    T = one if cfg.q1d == 4 else one / 3.0
+    st = pond.init(c1, one, zero, zero, T, device=device)
+    return st.f.reshape(cfg.Q)
+
+
+class _Equilibrium(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, rho, ux, uy, T, cfg: PondConfig):
+        st = pond.init(cfg, rho.detach(), ux.detach(), uy.detach(), T.detach(), device=rho.device)
+        ctx.cfg = cfg
+        ctx.save_for_backward(_weights(cfg, rho.device))
+        return st.f, st.g
+
+    @staticmethod
+    def backward(ctx, gf, gg):
+        (W,) = ctx.saved_tensors
+        grho = gux = guy = gT = None
+        if gf is not None:
+            grho = torch.einsum("p,pyx->yx", W, gf.double())
+        if gg is not None:
+            gux, guy, gT = gg[0], gg[1], gg[2]
+        return grho, gux, guy, gT, None
+
+
+def equilibrium_state(cfg: PondConfig, rho, ux, uy, T):
+    """(f, g) = pond_init(rho, u, T), differentiable in the four fields."""
+    return _Equilibrium.apply(rho, ux, uy, T, cfg)
+
+
+class PondRollout(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, f0, g0, tau, cfg: PondConfig, nsteps: int, checkpoint_every: int):
+        cfg_t = cfg.replace(tau=float(tau))
+        a = PondState(f0.detach().contiguous().clone(), g0.detach().contiguous().clone(),
+                      torch.zeros((cfg.ny, cfg.nx), dtype=torch.uint8, device=f0.device))
+        b = pond.empty_state(cfg_t, f0.device)
+        checkpoints = []
+        for k in range(nsteps):
+            if k % checkpoint_every == 0:
+                checkpoints.append((k, a.f.clone(), a.g.clone()))
+            pond.step(cfg_t, a, b)
+            a, b = b, a
+        ctx.cfg = cfg_t
+        ctx.nsteps = nsteps
+        ctx.K = checkpoint_every
+        ctx.checkpoints = checkpoints
+        return a.f.clone(), a.g.clone()
+
+    @staticmethod
+    def backward(ctx, gf, gg):
+        cfg = ctx.cfg
+        dev = ctx.checkpoints[0][1].device
+        af = (gf if gf is not None else torch.zeros_like(ctx.checkpoints[0][1])).double().contiguous()
+        ag = (gg if gg is not None else torch.zeros_like(ctx.checkpoints[0][2])).double().contiguous()
+        atau = torch.zeros(1, dtype=torch.float64, device=dev)
+        for k0, f_ck, g_ck in reversed(ctx.checkpoints):
+            k1 = min(k0 + ctx.K, ctx.nsteps)
+            # replay the segment, keeping every state and its pass counts
+            states = [PondState(f_ck.clone(), g_ck.clone(),
+                                torch.zeros((cfg.ny, cfg.nx), dtype=torch.uint8, device=dev))]
+            for _ in range(k0, k1):
+                out, _ = pond.step(cfg, states[-1])
+                states.append(out)
+            for k in range(k1 - k0, 0, -1):
+                af, ag = pond.step_adjoint(cfg, states[k - 1], states[k], af, ag, atau)
+        return af.to(ctx.checkpoints[0][1].dtype) if cfg.precision == pond.POND_F32_MIXED else af, \
+            ag, atau.reshape(()), None, None, None
+
+
+def rollout(f0, g0, tau, cfg: PondConfig, nsteps: int, checkpoint_every: int = 20):
+    """Differentiable nsteps-step rollout; ``tau`` is a 0-d float64 tensor."""
+    return PondRollout.apply(f0, g0, tau, cfg, nsteps, checkpoint_every)
+
+
+def kinetic_energy(f, g):
+    """J = sum over nodes of rho |u|^2 / 2 with rho = sum_p f_p and u the node gauge."""
+    rho = f.double().sum(0)
+    return 0.5 * (rho * (g[0] * g[0] + g[1] * g[1])).sum()

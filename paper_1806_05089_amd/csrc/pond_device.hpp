@@ -127,6 +127,30 @@ __device__ __forceinline__ void transfer_row(int k, double r, double d, double* 
   for (int i = 0; i < Q1; ++i) row[i] = lag_num<Q1>(k, r * Lat<Q1>::c(i) + d) * lag_inv_den<Q1>(k);
 }
 
+// Full per-axis transfer factor G[k*Q1 + i] = l_k(r c_i + d) (target speed k,
+// source speed i), from the differences e_m = z - c_m shared by all k.
+template <int Q1, class R>
+__device__ __forceinline__ void transfer_factor(R r, R d, R* G) {
+#pragma unroll
+  for (int i = 0; i < Q1; ++i) {
+    const R z = r * R(Lat<Q1>::c(i)) + d;
+    R e[Q1];
+#pragma unroll
+    for (int m = 0; m < Q1; ++m) e[m] = z - R(Lat<Q1>::c(m));
+    if constexpr (Q1 == 4) {
+      const R p01 = e[0] * e[1], p23 = e[2] * e[3];
+      G[0 * 4 + i] = (e[1] * p23) * R(lag_inv_den<4>(0));
+      G[1 * 4 + i] = (e[0] * p23) * R(lag_inv_den<4>(1));
+      G[2 * 4 + i] = (p01 * e[3]) * R(lag_inv_den<4>(2));
+      G[3 * 4 + i] = (p01 * e[2]) * R(lag_inv_den<4>(3));
+    } else {
+      G[0 * 3 + i] = (e[1] * e[2]) * R(lag_inv_den<3>(0));
+      G[1 * 3 + i] = (e[0] * e[2]) * R(lag_inv_den<3>(1));
+      G[2 * 3 + i] = (e[0] * e[1]) * R(lag_inv_den<3>(2));
+    }
+  }
+}
+
 // Row of the transfer factor for the basis polynomial with coefficients P.
 template <int Q1>
 __device__ __forceinline__ void transfer_row_coef(const LagRow& P, double r, double d, double* row) {
@@ -161,6 +185,50 @@ __device__ __forceinline__ int wrap_index(int i, int n, int bc) {
     return r < 0 ? r + n : r;
   }
   return i < 0 ? 0 : (i >= n ? n - 1 : i);
+}
+
+// Derivatives of the interpolation weights with respect to t.
+__device__ __forceinline__ void interp_weights_d(double t, double* a, double* da) {
+  const double t0 = t, t1 = t - 1.0, t2 = t - 2.0, t3 = t - 3.0;
+  a[0] = t1 * t2 * t3 * (-1.0 / 6.0);
+  a[1] = t0 * t2 * t3 * 0.5;
+  a[2] = t0 * t1 * t3 * (-0.5);
+  a[3] = t0 * t1 * t2 * (1.0 / 6.0);
+  da[0] = (t2 * t3 + t1 * t3 + t1 * t2) * (-1.0 / 6.0);
+  da[1] = (t2 * t3 + t0 * t3 + t0 * t2) * 0.5;
+  da[2] = (t1 * t3 + t0 * t3 + t0 * t1) * (-0.5);
+  da[3] = (t1 * t2 + t0 * t2 + t0 * t1) * (1.0 / 6.0);
+}
+
+// Derivative of the Lagrange basis polynomial with Horner coefficients P.
+__device__ __forceinline__ double lag_deriv(const LagRow& P, double z) {
+  return fma(fma(3.0 * P.l3, z, 2.0 * P.l2), z, P.l1);
+}
+
+// dG[k*Q1 + i] = l_k'(r c_i + d) for the full per-axis factor.
+template <int Q1>
+__device__ __forceinline__ void transfer_factor_deriv(double r, double d, double* dG) {
+#pragma unroll
+  for (int i = 0; i < Q1; ++i) {
+    const double z = r * Lat<Q1>::c(i) + d;
+    double e[Q1];
+#pragma unroll
+    for (int m = 0; m < Q1; ++m) e[m] = z - Lat<Q1>::c(m);
+#pragma unroll
+    for (int k = 0; k < Q1; ++k) {
+      double acc = 0.0;
+#pragma unroll
+      for (int m = 0; m < Q1; ++m) {
+        if (m == k) continue;
+        double p = 1.0;
+#pragma unroll
+        for (int mm = 0; mm < Q1; ++mm)
+          if (mm != k && mm != m) p *= e[mm];
+        acc += p;
+      }
+      dG[k * Q1 + i] = acc * lag_inv_den<Q1>(k);
+    }
+  }
 }
 
 // Error-free sum (Knuth TwoSum) for compensated accumulation.

@@ -3,15 +3,21 @@
 //
 // Mapping.  One lane owns one node; a wave covers an 8 x 8 tile of nodes
 // (nodes that need many predictor-corrector passes cluster along fronts, and
-// square wave tiles cut the number of waves a front crosses).  A block of
-// TX x TY nodes first stages a halo window of the state at t - dt in LDS:
-// populations f (FT) and the gauge (u_x, u_y, sqrt(theta)) (double) of
-// (TX + 2H) x (TY + 2H) nodes, placed around the stencils of the block's seed
-// gauges (so a fast uniform drift shifts the window instead of widening it).
-// The pass loop then gathers every collocation point from LDS; a point outside
-// the window (a corrector pass that moved far, or a block whose stencils span
-// more than the window) is read from HBM instead.  After the staging barrier
-// the lanes iterate independently.
+// square wave tiles cut the number of waves a front crosses).
+//
+// Common-frame halo window.  A block of TX x TY nodes stages a
+// (TX + 2H) x (TY + 2H) window of the state at t - dt in LDS, placed around the
+// stencils of the block's seed gauges (a uniform drift shifts the window
+// instead of widening it).  While staging, every window node's populations are
+// moved from the node's own gauge into one reference gauge lambda_B of the
+// block (the mean seed gauge) by eq. (4).  Transfer matrices compose
+// (G_{B->n} G_{s->B} = G_{s->n}), so inside the pass loop the transform of a
+// collocation point s into the node's gauge lambda_n is G_{B->n} applied to
+// the staged f^B_s: the per-axis factors of G_{B->n} are built once per node
+// and pass, and a (population, collocation point) pair costs 16 LDS reads and
+// 20 multiply-adds.  A collocation point outside the window is read from HBM
+// and transformed directly with G_{s->n}.  After staging the lanes iterate
+// independently (no further barriers).
 #include <hip/hip_runtime.h>
 #include <limits.h>
 #include <math.h>
@@ -29,41 +35,51 @@ struct TileShape {
   static constexpr int WN = WX * WY;
   static constexpr int NT = TX * TY;
   static constexpr int NW = NT / 64;
-  static constexpr size_t lds_bytes = (size_t)Q1 * Q1 * WN * sizeof(FT) + 3 * WN * sizeof(double);
+  static constexpr size_t lds_bytes = (size_t)Q1 * Q1 * WN * sizeof(FT);
   static_assert(TX % 8 == 0 && TY % 8 == 0, "waves are 8 x 8 node tiles");
-  static_assert(lds_bytes + 64 <= 160 * 1024, "window exceeds the 160 KiB LDS of a CU");
+  static_assert(lds_bytes + 1024 <= 160 * 1024, "window exceeds the 160 KiB LDS of a CU");
 };
-
-// Block-wide minimum of four ints (maxima are passed negated).
-template <int NW>
-__device__ __forceinline__ void block_min4(int v[4], int* s_red) {
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-      const int o = __shfl_xor(v[k], off);
-      v[k] = o < v[k] ? o : v[k];
-    }
-  }
-  if ((threadIdx.x & 63) == 0) {
-#pragma unroll
-    for (int k = 0; k < 4; ++k) s_red[k * NW + (threadIdx.x >> 6)] = v[k];
-  }
-  __syncthreads();
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    int m = s_red[k * NW];
-#pragma unroll
-    for (int w = 1; w < NW; ++w) m = s_red[k * NW + w] < m ? s_red[k * NW + w] : m;
-    v[k] = m;
-  }
-}
 
 // Floor of a departure coordinate as int, saturated so that absurd gauges
 // (non-finite or |x| > 1e9) cannot overflow the conversion.
 __device__ __forceinline__ int sat_floor(double x) {
   x = fmin(fmax(x, -1.0e9), 1.0e9);
   return isfinite(x) ? int(floor(x)) : 0;
+}
+
+// Block reduction: minimum of four ints, sum of four doubles.
+template <int NW>
+__device__ __forceinline__ void block_reduce(int v[4], double a[4], int* s_i, double* s_d) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int o = __shfl_xor(v[k], off);
+      v[k] = o < v[k] ? o : v[k];
+      a[k] += __shfl_xor(a[k], off);
+    }
+  }
+  const int wave = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      s_i[k * NW + wave] = v[k];
+      s_d[k * NW + wave] = a[k];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    int m = s_i[k * NW];
+    double t = s_d[k * NW];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) {
+      m = s_i[k * NW + w] < m ? s_i[k * NW + w] : m;
+      t += s_d[k * NW + w];
+    }
+    v[k] = m;
+    a[k] = t;
+  }
 }
 
 template <int Q1, class FT, int TX, int TY, int H>
@@ -74,8 +90,8 @@ k_step(StepArgs A) {
   using TS = TileShape<Q1, FT, TX, TY, H>;
   constexpr int WX = TS::WX, WY = TS::WY, WN = TS::WN, NT = TS::NT;
   __shared__ FT s_f[Q * WN];
-  __shared__ double s_g[3 * WN];
-  __shared__ int s_red[4 * TS::NW];
+  __shared__ int s_ri[4 * TS::NW];
+  __shared__ double s_rd[4 * TS::NW];
 
   // Block -> tile: blocks are dealt to the 8 XCDs round-robin; renumber so
   // that consecutive tiles (which share halo data) run on the same XCD.
@@ -111,19 +127,34 @@ k_step(StepArgs A) {
     }
   }
 
-  // ---- window placement from the seed stencils (one node of margin) ----
+  // ---- window placement and reference gauge from the seed gauges ----
   int wx0, wy0;
+  double uxB, uyB, sB;
   {
     int v[4] = {INT_MAX, INT_MAX, INT_MAX, INT_MAX};
-    const double sp = sqrt(T * L::inv_TL) * L::c(Q1 - 1);
-    if (active && isfinite(sp) && isfinite(ux) && isfinite(uy)) {
+    double a[4] = {0.0, 0.0, 0.0, 0.0};
+    const double s0 = sqrt(T * L::inv_TL);
+    const double sp = s0 * L::c(Q1 - 1);
+    if (active && isfinite(sp) && s0 > 0.0 && isfinite(ux) && isfinite(uy) &&
+        fabs(ux) < 1e9 && fabs(uy) < 1e9) {
       v[0] = sat_floor(double(X) - ux - sp) - 2;
       v[1] = -(sat_floor(double(X) - ux + sp) + 3);
       v[2] = sat_floor(double(Y) - uy - sp) - 2;
       v[3] = -(sat_floor(double(Y) - uy + sp) + 3);
+      a[0] = ux;
+      a[1] = uy;
+      a[2] = s0;
+      a[3] = 1.0;
     }
-    block_min4<TS::NW>(v, s_red);
-    if (v[0] == INT_MAX) {  // no usable seed in the block: centre on the tile
+    block_reduce<TS::NW>(v, a, s_ri, s_rd);
+    if (a[3] > 0.0) {
+      uxB = a[0] / a[3];
+      uyB = a[1] / a[3];
+      sB = a[2] / a[3];
+    } else {  // no usable seed in the block: any reference gauge is exact
+      uxB = 0.0;
+      uyB = 0.0;
+      sB = 1.0;
       v[0] = bx0 - H;
       v[1] = -(bx0 + TX + H - 1);
       v[2] = by0 - H;
@@ -134,17 +165,43 @@ k_step(StepArgs A) {
     wx0 = nxn <= WX ? xlo - (WX - nxn) / 2 : (int)(((long long)xlo + xhi) / 2) - WX / 2;
     wy0 = nyn <= WY ? ylo - (WY - nyn) / 2 : (int)(((long long)ylo + yhi) / 2) - WY / 2;
   }
-  // ---- stage the window (rows of the window are coalesced along x) ----
-  for (int k = tid; k < WN; k += NT) {
-    const int wy = k / WX, wx = k - wy * WX;
-    const int sx = wrap_index(wx0 + wx, A.nx, A.bc_x);
-    const int sy = wrap_index(wy0 + wy, A.ny, A.bc_y);
-    const size_t src = (size_t)sy * A.nx + sx;
+
+  // ---- stage the window in the reference gauge (eq. 4, G_{s->B}) ----
+  {
+    const double inv_sB = 1.0 / sB;
+    for (int k = tid; k < WN; k += NT) {
+      const int wy = k / WX, wx = k - wy * WX;
+      const int sx = wrap_index(wx0 + wx, A.nx, A.bc_x);
+      const int sy = wrap_index(wy0 + wy, A.ny, A.bc_y);
+      const size_t src = (size_t)sy * A.nx + sx;
+      double f[Q];
 #pragma unroll
-    for (int p = 0; p < Q; ++p) s_f[p * WN + k] = fin[(size_t)p * plane + src];
-    s_g[k] = gin[src];
-    s_g[WN + k] = gin[plane + src];
-    s_g[2 * WN + k] = sqrt(gin[2 * plane + src] * L::inv_TL);
+      for (int p = 0; p < Q; ++p) f[p] = double(fin[(size_t)p * plane + src]);
+      const double ss = sqrt(gin[2 * plane + src] * L::inv_TL);
+      const double r = ss * inv_sB;
+      double Gx[Q], Gy[Q];
+      transfer_factor<Q1, double>(r, (gin[src] - uxB) * inv_sB, Gx);
+      transfer_factor<Q1, double>(r, (gin[plane + src] - uyB) * inv_sB, Gy);
+      double Hm[Q];  // Hm[i][l] = sum_j Gy[l][j] f[i][j]
+#pragma unroll
+      for (int i = 0; i < Q1; ++i)
+#pragma unroll
+        for (int l = 0; l < Q1; ++l) {
+          double h = 0.0;
+#pragma unroll
+          for (int j = 0; j < Q1; ++j) h = fma(Gy[l * Q1 + j], f[i * Q1 + j], h);
+          Hm[i * Q1 + l] = h;
+        }
+#pragma unroll
+      for (int kk = 0; kk < Q1; ++kk)
+#pragma unroll
+        for (int l = 0; l < Q1; ++l) {
+          double t = 0.0;
+#pragma unroll
+          for (int i = 0; i < Q1; ++i) t = fma(Gx[kk * Q1 + i], Hm[i * Q1 + l], t);
+          s_f[(kk * Q1 + l) * WN + k] = FT(t);
+        }
+    }
   }
   __syncthreads();
 
@@ -159,92 +216,99 @@ k_step(StepArgs A) {
       const double s = sqrt(T * L::inv_TL);
       const double inv_s = 1.0 / s;
       const double uxs = ux * inv_s, uys = uy * inv_s;
-#pragma unroll
-      for (int p = 0; p < Q; ++p) ft[p] = FT(0);
+      // a4 (window part): G_{B->n} rows are l_k(rB c + dB) per axis.
+      const double rB = sB * inv_s;
+      const double dBx = (uxB - ux) * inv_s, dBy = (uyB - uy) * inv_s;
 
-      // (x speed i, stencil column n, y speed j, stencil row m) one at a time;
-      // the four indices are wave-uniform, so the loops stay rolled and one
-      // collocation point is live in registers.
+      // (y speed j, x speed i, stencil column n) are wave-uniform rolled
+      // loops; the four stencil rows of one column are unrolled.
 #pragma unroll 1
-      for (int i = 0; i < Q1; ++i) {
-        // a2 + a3 (x axis): the departure abscissa depends on c_i only.
-        const double xd = double(X) - (s * speed_rt<Q1>(i) + ux);
-        const LagRow Pi = lag_row<Q1>(i);
-        const double fl = floor(xd);
-        double ax[4];
-        interp_weights(xd - (fl - 1.0), ax);
-        const int x0 = sat_floor(fl) - 1;
-        FT acc_row[Q1];
+      for (int j = 0; j < Q1; ++j) {
+        // a2 + a3 (y axis): the departure ordinate depends on c_j only.
+        const double yd = double(Y) - (s * speed_rt<Q1>(j) + uy);
+        const double fly = floor(yd);
+        double ay[4];
+        interp_weights(yd - (fly - 1.0), ay);
+        const int y0 = sat_floor(fly) - 1;
+        const int ly0 = y0 - wy0;
+        const LagRow Pj = lag_row<Q1>(j);
+        FT gby[Q1];
+        {
+          double row[Q1];
+          transfer_row_coef<Q1>(Pj, rB, dBy, row);
 #pragma unroll
-        for (int j = 0; j < Q1; ++j) acc_row[j] = FT(0);
+          for (int jp = 0; jp < Q1; ++jp) gby[jp] = FT(row[jp]);
+        }
 #pragma unroll 1
-        for (int n = 0; n < 4; ++n) {
-          const int gx = x0 + n;
-          const int lx = gx - wx0;
-          const bool in_x = (unsigned)lx < (unsigned)WX;
-          const double axn = n == 0 ? ax[0] : n == 1 ? ax[1] : n == 2 ? ax[2] : ax[3];
+        for (int i = 0; i < Q1; ++i) {
+          // a2 + a3 (x axis)
+          const double xd = double(X) - (s * speed_rt<Q1>(i) + ux);
+          const double fl = floor(xd);
+          double ax[4];
+          interp_weights(xd - (fl - 1.0), ax);
+          const int x0 = sat_floor(fl) - 1;
+          const LagRow Pi = lag_row<Q1>(i);
+          FT gbx[Q1];
+          {
+            double row[Q1];
+            transfer_row_coef<Q1>(Pi, rB, dBx, row);
+#pragma unroll
+            for (int ip = 0; ip < Q1; ++ip) gbx[ip] = FT(row[ip]);
+          }
+          FT acc_ij = FT(0);
 #pragma unroll 1
-          for (int j = 0; j < Q1; ++j) {
-            // a2 + a3 (y axis)
-            const double yd = double(Y) - (s * speed_rt<Q1>(j) + uy);
-            const LagRow Pj = lag_row<Q1>(j);
-            const double fly = floor(yd);
-            double ay[4];
-            interp_weights(yd - (fly - 1.0), ay);
-            const int y0 = sat_floor(fly) - 1;
-            FT acc_j = FT(0);
-#pragma unroll 1
+          for (int n = 0; n < 4; ++n) {
+            const int lx = x0 + n - wx0;
+            const bool in_x = (unsigned)lx < (unsigned)WX;
+            const double axn = n == 0 ? ax[0] : n == 1 ? ax[1] : n == 2 ? ax[2] : ax[3];
+            FT col = FT(0);
+#pragma unroll
             for (int m = 0; m < 4; ++m) {
-              const int gy = y0 + m;
-              const int ly = gy - wy0;
-              const double aym = m == 0 ? ay[0] : m == 1 ? ay[1] : m == 2 ? ay[2] : ay[3];
-              // the collocation point (gx, gy): LDS window or HBM
-              FT fs[Q];
-              double sux, suy, ss;
+              const int ly = ly0 + m;
+              FT val;
               if (in_x && (unsigned)ly < (unsigned)WY) {
+                // a4 + a5: [G_{B->n} f^B_s]_(i,j) from the staged window
                 const int k = ly * WX + lx;
+                FT t = FT(0);
 #pragma unroll
-                for (int p = 0; p < Q; ++p) fs[p] = s_f[p * WN + k];
-                sux = s_g[k];
-                suy = s_g[WN + k];
-                ss = s_g[2 * WN + k];
+                for (int ip = 0; ip < Q1; ++ip) {
+                  FT h = FT(0);
+#pragma unroll
+                  for (int jp = 0; jp < Q1; ++jp) h += gby[jp] * s_f[(ip * Q1 + jp) * WN + k];
+                  t += gbx[ip] * h;
+                }
+                val = t;
               } else {
-                const int sx = wrap_index(gx, A.nx, A.bc_x);
-                const int sy = wrap_index(gy, A.ny, A.bc_y);
+                // outside the window: [G_{s->n} f_s]_(i,j) from HBM
+                const int sx = wrap_index(x0 + n, A.nx, A.bc_x);
+                const int sy = wrap_index(y0 + m, A.ny, A.bc_y);
                 const size_t src = (size_t)sy * A.nx + sx;
+                const double r = sqrt(gin[2 * plane + src] * L::inv_TL) * inv_s;
+                double gxr[Q1], gyr[Q1];
+                transfer_row_coef<Q1>(Pi, r, fma(gin[src], inv_s, -uxs), gxr);
+                transfer_row_coef<Q1>(Pj, r, fma(gin[plane + src], inv_s, -uys), gyr);
+                FT t = FT(0);
 #pragma unroll
-                for (int p = 0; p < Q; ++p) fs[p] = fin[(size_t)p * plane + src];
-                sux = gin[src];
-                suy = gin[plane + src];
-                ss = sqrt(gin[2 * plane + src] * L::inv_TL);
+                for (int ip = 0; ip < Q1; ++ip) {
+                  FT h = FT(0);
+#pragma unroll
+                  for (int jp = 0; jp < Q1; ++jp)
+                    h += FT(gyr[jp]) * fin[(size_t)(ip * Q1 + jp) * plane + src];
+                  t += FT(gxr[ip]) * h;
+                }
+                val = t;
               }
-              // a4: rows i and j of the transfer factors, z = r c + d
-              const double r = ss * inv_s;
-              double gxr[Q1], gyr[Q1];
-              transfer_row_coef<Q1>(Pi, r, fma(sux, inv_s, -uxs), gxr);
-              transfer_row_coef<Q1>(Pj, r, fma(suy, inv_s, -uys), gyr);
-              FT acc = FT(0);
-#pragma unroll
-              for (int ip = 0; ip < Q1; ++ip) {
-                FT h = FT(0);
-#pragma unroll
-                for (int jp = 0; jp < Q1; ++jp) h += FT(gyr[jp]) * fs[ip * Q1 + jp];
-                acc += FT(gxr[ip]) * h;
-              }
-              // a5: interpolation weight of this collocation point
-              acc_j += FT(axn * aym) * acc;
+              // a5: weight of row m
+              col += FT(ay[m]) * val;
             }
+            acc_ij += FT(axn) * col;
+          }
+#pragma unroll
+          for (int ii = 0; ii < Q1; ++ii)
 #pragma unroll
             for (int jj = 0; jj < Q1; ++jj)
-              if (jj == j) acc_row[jj] += acc_j;
-          }
+              if (ii == i && jj == j) ft[ii * Q1 + jj] = acc_ij;
         }
-#pragma unroll
-        for (int ii = 0; ii < Q1; ++ii)
-          if (ii == i) {
-#pragma unroll
-            for (int j = 0; j < Q1; ++j) ft[ii * Q1 + j] = acc_row[j];
-          }
       }
 
       // a6: moments in the peculiar frame of lambda_n (compensated sums).
@@ -305,34 +369,31 @@ k_step(StepArgs A) {
       // a8: f^{lambda_n} -> lambda_{n+1}, one full Kronecker transform.
       const double s = sqrt(T * L::inv_TL), s1 = sqrt(T1 * L::inv_TL);
       const double inv_s1 = 1.0 / s1, r = s * inv_s1;
+      double Rx[Q], Ry[Q];
+      transfer_factor<Q1, double>(r, (ux - ux1) * inv_s1, Rx);
+      transfer_factor<Q1, double>(r, (uy - uy1) * inv_s1, Ry);
       FT Hm[Q];  // Hm[i][l] = sum_j Ry[l][j] ft[i][j]
 #pragma unroll
-      for (int l = 0; l < Q1; ++l) {
-        double ry[Q1];
-        transfer_row<Q1>(l, r, (uy - uy1) * inv_s1, ry);
+      for (int i = 0; i < Q1; ++i)
 #pragma unroll
-        for (int i = 0; i < Q1; ++i) {
+        for (int l = 0; l < Q1; ++l) {
           FT h = FT(0);
 #pragma unroll
-          for (int j = 0; j < Q1; ++j) h += FT(ry[j]) * ft[i * Q1 + j];
+          for (int j = 0; j < Q1; ++j) h += FT(Ry[l * Q1 + j]) * ft[i * Q1 + j];
           Hm[i * Q1 + l] = h;
         }
-      }
       // a9: BGK towards rho W (eq. 18), a10: store.
       const FT omega = FT(1.0 / A.tau);
 #pragma unroll
-      for (int k = 0; k < Q1; ++k) {
-        double rx[Q1];
-        transfer_row<Q1>(k, r, (ux - ux1) * inv_s1, rx);
+      for (int k = 0; k < Q1; ++k)
 #pragma unroll
         for (int l = 0; l < Q1; ++l) {
           FT fr = FT(0);
 #pragma unroll
-          for (int i = 0; i < Q1; ++i) fr += FT(rx[i]) * Hm[i * Q1 + l];
+          for (int i = 0; i < Q1; ++i) fr += FT(Rx[k * Q1 + i]) * Hm[i * Q1 + l];
           const FT feq = FT(rho1 * (L::w(k) * L::w(l)));
           fout[(size_t)(k * Q1 + l) * plane + node] = fr + omega * (feq - fr);
         }
-      }
       A.g_out[node] = ux1;
       A.g_out[plane + node] = uy1;
       A.g_out[2 * plane + node] = T1;
@@ -362,15 +423,22 @@ k_step(StepArgs A) {
   }
 }
 
-// Tile shapes: TX x TY nodes per block, halo H.  FP64: 16 x 16, H = 5
-// (26 x 26 window, 103 KiB LDS, one block per CU).  FP32-mixed: same window
-// in 59 KiB (two blocks per CU).
+// Tile shapes (TX x TY nodes per block, halo H).  D2Q16: 32 x 16 nodes with a
+// 42 x 26 window: 140 KiB of LDS in FP64 (one block, 8 waves per CU) and
+// 70 KiB in FP32 (two blocks per CU).
+#ifndef POND_TILE_X
+#define POND_TILE_X 32
+#endif
+#ifndef POND_TILE_Y
+#define POND_TILE_Y 16
+#endif
+#ifndef POND_HALO
+#define POND_HALO 5
+#endif
 template <int Q1, class FT>
-struct StepTile;
-template <> struct StepTile<4, double> { static constexpr int TX = 16, TY = 16, H = 5; };
-template <> struct StepTile<4, float> { static constexpr int TX = 16, TY = 16, H = 5; };
-template <> struct StepTile<3, double> { static constexpr int TX = 16, TY = 16, H = 4; };
-template <> struct StepTile<3, float> { static constexpr int TX = 16, TY = 16, H = 4; };
+struct StepTile {
+  static constexpr int TX = POND_TILE_X, TY = POND_TILE_Y, H = Q1 == 4 ? POND_HALO : 4;
+};
 
 template <int Q1, class FT>
 hipError_t launch_step_t(const StepArgs& a, hipStream_t s) {
