@@ -2,17 +2,21 @@
 
 Workload: the four-quadrant 2-D Riemann problem (D2Q16, zero-gradient edges,
 tau = 0.55, seed 3) on a 1024^2 grid, run from its initial state for K steps.
-A "step" is one pond_step launch: propagation with the predictor-corrector
-gauge iteration, then BGK.  MLUPS = nodes * steps / seconds / 1e6 with the
-state resident in HBM; timed with HIP events on the launch stream.
+A "step" is one pond_step call: propagation with the adaptive predictor-
+corrector gauge iteration, then BGK.  MLUPS = nodes * steps / seconds / 1e6
+with the state resident in HBM, timed with HIP events on the launch stream.
 
-Prints one JSON line (rank 0).  The FP64 path gives `value`; the FP32-mixed
-path, its error against FP64 and the adjoint/forward time ratio are reported
-beside it, with the oracle timed on host cores as `cpu_baseline`.
+Prints one JSON line.  The FP64 path gives `value`; the FP32-mixed path, its
+error against FP64, the adjoint/forward time ratios and the oracle timed on
+host cores (`cpu_baseline`) are reported beside it.
+
+Other modes (used for profiling, each prints its own line):
+  --kernel-only   FP64 steps only, no replays or baselines (for rocprofv3)
+  --copy-probe    a plain device copy of known size (HBM counter calibration)
 """
 import argparse
+import hashlib
 import json
-import math
 import os
 import sys
 import time
@@ -24,21 +28,26 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-from paper_1806_05089_amd import pond, workloads  # noqa: E402
+from paper_1806_05089_amd import autograd, pond, workloads  # noqa: E402
 
-# Algorithmic flop count (see the design notes): per node and predictor-corrector
-# pass, 16 populations x 16 collocation points x 42 flops for the row-Kronecker
-# contraction and weighted accumulate, plus 16 x 16 x 64 flops for the two
-# transfer rows (4 entries x (linear map + cubic Horner) each); per node and
-# step, 560 flops for the regauge and the BGK relaxation.
+# Algorithmic flop count per node and predictor-corrector pass: 16 populations
+# x 16 collocation points x (42 flops for the row-Kronecker contraction and
+# weighted accumulate + 64 flops for the two transfer rows built per pair in
+# the direct form); per node and step, 560 flops for the regauge and BGK.
 FLOPS_PER_NODE_PASS = 16 * 16 * 42 + 16 * 16 * 64
 FLOPS_PER_NODE_STEP = 560
 PEAK_FP64_TFLOPS = 78.6   # MI355X vector FP64: 256 CU x 2.4 GHz x 64 lanes x 2
 PEAK_FP32_TFLOPS = 157.3  # MI355X published FP32 peak
+STEP_SOURCE = os.path.join(ROOT, "paper_1806_05089_amd", "csrc", "pond_step.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_traffic.json")
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
+
+
+def source_digest():
+    return hashlib.sha256(open(STEP_SOURCE, "rb").read()).hexdigest()[:16]
 
 
 def make_cfg(w, precision):
@@ -50,8 +59,8 @@ def make_cfg(w, precision):
     return cfg
 
 
-def run_steps(cfg, w, steps, warmup, count_passes=False):
-    """Warm up on a throwaway copy, then time `steps` steps from the initial state."""
+def timed_steps(cfg, w, steps, warmup):
+    """Warm up on a throwaway run, then time `steps` steps from the initial state."""
     a = pond.init(cfg, w.rho, w.ux, w.uy, w.T)
     b = pond.empty_state(cfg)
     for _ in range(warmup):
@@ -68,20 +77,72 @@ def run_steps(cfg, w, steps, warmup, count_passes=False):
         a, b = b, a
     e1.record(stream)
     torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1)
-    passes = None
-    if count_passes:
-        # replay with per-step statistics to count the predictor-corrector passes
-        a = pond.init(cfg, w.rho, w.ux, w.uy, w.T)
-        total = 0.0
-        nonconv = 0
-        for _ in range(steps):
-            _, st = pond.step(cfg, a, b, stats=True)
-            total += st["mean_iters"]
-            nonconv += st["nonconverged"]
-            a, b = b, a
-        passes = {"mean_passes": total / steps, "nonconverged_node_steps": nonconv}
-    return ms, a, passes
+    return e0.elapsed_time(e1), a, b
+
+
+def count_passes(cfg, w, steps):
+    """Replay the run with per-step statistics (predictor-corrector passes)."""
+    a = pond.init(cfg, w.rho, w.ux, w.uy, w.T)
+    b = pond.empty_state(cfg)
+    total = 0.0
+    nonconv = 0
+    for _ in range(steps):
+        _, st = pond.step(cfg, a, b, stats=True)
+        total += st["mean_iters"]
+        nonconv += st["nonconverged"]
+        a, b = b, a
+    return {"mean_passes": total / steps, "nonconverged_node_steps": nonconv}
+
+
+def adjoint_ratio_1024(cfg, state, reps=3):
+    """Time of one pond_step_adjoint vs one pond_step about the same state."""
+    out, _ = pond.step(cfg, state)
+    g = torch.Generator(device="cuda").manual_seed(0)
+    wf = torch.randn(out.f.shape, dtype=torch.float64, device="cuda", generator=g)
+    wg = torch.randn(out.g.shape, dtype=torch.float64, device="cuda", generator=g)
+    atau = torch.zeros(1, dtype=torch.float64, device="cuda")
+    pond.step_adjoint(cfg, state, out, wf, wg, atau)
+    torch.cuda.synchronize()
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    e[0].record()
+    for _ in range(reps):
+        pond.step(cfg, state, out)
+    e[1].record()
+    e[2].record()
+    for _ in range(reps):
+        pond.step_adjoint(cfg, state, out, wf, wg, atau)
+    e[3].record()
+    torch.cuda.synchronize()
+    fwd = e[0].elapsed_time(e[1]) / reps
+    adj = e[2].elapsed_time(e[3]) / reps
+    return {"forward_ms": fwd, "adjoint_ms": adj, "ratio": adj / fwd}
+
+
+def adjoint_ratio_tgv128():
+    """Compressible Taylor-Green 128^2 (Mach 0.5, FP32-mixed), 200 steps,
+    checkpoints every 20: forward rollout time vs backward time."""
+    w = workloads.compressible_taylor_green(128, seed=1)
+    cfg = pond.PondConfig(nx=128, ny=128, precision=pond.POND_F32_MIXED, tau=0.6,
+                          eps_abs=1e-6, eps_rel=1e-5, max_iter=20)
+    dev = torch.device("cuda")
+    rho = torch.tensor(w.rho, dtype=torch.float64, device=dev)
+    ux = torch.tensor(w.ux, dtype=torch.float64, device=dev, requires_grad=True)
+    uy = torch.tensor(w.uy, dtype=torch.float64, device=dev, requires_grad=True)
+    T = torch.tensor(w.T, dtype=torch.float64, device=dev)
+    tau = torch.tensor(0.6, dtype=torch.float64, device=dev, requires_grad=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    f0, g0 = autograd.equilibrium_state(cfg, rho, ux, uy, T)
+    fT, gT = autograd.rollout(f0, g0, tau, cfg, 200, checkpoint_every=20)
+    J = autograd.kinetic_energy(fT, gT)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    J.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    return {"forward_s": t1 - t0, "backward_s": t2 - t1, "ratio": (t2 - t1) / (t1 - t0),
+            "dJ_dtau": float(tau.grad.item()), "dJ_dnu": float(tau.grad.item()) / 1.0,
+            "note": "backward includes the checkpoint replays (one extra forward per step)"}
 
 
 def cpu_baseline(cfg, state, sample_nodes, seed=0):
@@ -113,6 +174,28 @@ def field_errors(cfg64, s64, cfg32, s32):
     return out
 
 
+def traffic_per_launch(n_launch_nodes):
+    """HBM bytes per step launch from the committed counter summary, if it was
+    taken on the current step kernel source; else None."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    rec = json.load(open(TRAFFIC_FILE))
+    if rec.get("source_sha256_16") != source_digest():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def copy_probe():
+    n = 1 << 27  # 1 GiB of float64
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": n * 8, "copy_probe_bytes_written": n * 8,
+                      "launches": 3}), flush=True)
+
+
 def main():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
@@ -121,25 +204,35 @@ def main():
     p.add_argument("--size", type=int, default=1024)
     p.add_argument("--no-fp32", action="store_true")
     p.add_argument("--no-cpu-baseline", action="store_true")
-    p.add_argument("--cpu-sample", type=int, default=150000)
+    p.add_argument("--no-adjoint", action="store_true")
+    p.add_argument("--cpu-sample", type=int, default=1000000)
     p.add_argument("--no-pass-count", action="store_true")
+    p.add_argument("--kernel-only", action="store_true")
+    p.add_argument("--copy-probe", action="store_true")
     args = p.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the PonD step here has no multi-GPU path "
-              "(halo exchange is a design note, not built); run with --gpus 1", file=sys.stderr)
+              "(the halo exchange is a design note, not built); run with --gpus 1",
+              file=sys.stderr)
         sys.exit(2)
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
+    if args.copy_probe:
+        copy_probe()
+        return
 
     w = workloads.riemann2d(args.size, seed=3)
     nodes = args.size * args.size
     cfg64 = make_cfg(w, pond.POND_F64)
     log(f"[bench] FP64 {args.size}^2, warmup {args.warmup}, steps {args.steps}")
-    ms64, s64, passes64 = run_steps(cfg64, w, args.steps, args.warmup,
-                                    count_passes=not args.no_pass_count)
+    ms64, s64, s64_prev = timed_steps(cfg64, w, args.steps, args.warmup)
     mlups64 = nodes * args.steps / (ms64 * 1e-3) / 1e6
-    log(f"[bench] FP64 {ms64 / args.steps:.3f} ms/step, {mlups64:.1f} MLUPS, passes {passes64}")
+    log(f"[bench] FP64 {ms64 / args.steps:.3f} ms/step, {mlups64:.1f} MLUPS")
+    if args.kernel_only:
+        print(json.dumps({"kernel_only": True, "ms_per_step": ms64 / args.steps,
+                          "value": mlups64, "unit": "MLUPS"}), flush=True)
+        return
 
     result = {
         "metric": "PonD MLUPS (D2Q16, 1024^2) FP32 vs FP64 at stated error; adjoint/forward ratio",
@@ -154,13 +247,14 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"riemann2d four-quadrant 2-D Riemann problem, D2Q16, "
+        "config": {"workload": f"riemann2d: four-quadrant 2-D Riemann problem, D2Q16, "
                                f"{args.size}x{args.size}, zero-gradient edges, tau 0.55, seed 3, "
-                               f"adaptive PC (App. E tolerances 1e-12/1e-10, cap 20), "
-                               f"{args.steps} steps from the initial state",
+                               f"adaptive predictor-corrector (App. E tolerances 1e-12/1e-10, "
+                               f"cap 20), {args.steps} steps from the initial state",
                    "nx": args.size, "ny": args.size, "parallelism": "single GPU"},
     }
-    if passes64:
+    if not args.no_pass_count:
+        passes64 = count_passes(cfg64, w, args.steps)
         node_passes = passes64["mean_passes"] * nodes
         flops = FLOPS_PER_NODE_PASS * node_passes + FLOPS_PER_NODE_STEP * nodes
         achieved = flops / (ms64 / args.steps * 1e-3) / 1e12
@@ -168,21 +262,23 @@ def main():
         result["nonconverged_node_steps"] = passes64["nonconverged_node_steps"]
         result["roofline"] = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
                               "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
-                              "traffic": None, "kernel": "k_step<4,double>",
-                              "flops_per_node_pass": FLOPS_PER_NODE_PASS}
+                              "traffic": traffic_per_launch(nodes),
+                              "kernel": "k_step<4,double> + k_step_tail<4,double> (per step)",
+                              "flops_per_node_pass": FLOPS_PER_NODE_PASS,
+                              "flops_per_launch": flops}
 
     if not args.no_fp32:
         cfg32 = make_cfg(w, pond.POND_F32_MIXED)
         log("[bench] FP32-mixed")
-        ms32, s32, passes32 = run_steps(cfg32, w, args.steps, args.warmup,
-                                        count_passes=not args.no_pass_count)
+        ms32, s32, _ = timed_steps(cfg32, w, args.steps, args.warmup)
         mlups32 = nodes * args.steps / (ms32 * 1e-3) / 1e6
         log(f"[bench] FP32 {ms32 / args.steps:.3f} ms/step, {mlups32:.1f} MLUPS")
         fp32 = {"value": mlups32, "unit": "MLUPS", "ms_per_step": ms32 / args.steps,
                 "speedup_vs_fp64": mlups32 / mlups64,
                 "error_vs_fp64_at_last_step": field_errors(cfg64, s64, cfg32, s32),
                 "tolerances": {"eps_abs": cfg32.eps_abs, "eps_rel": cfg32.eps_rel}}
-        if passes32:
+        if not args.no_pass_count:
+            passes32 = count_passes(cfg32, w, args.steps)
             fp32["mean_pc_passes"] = passes32["mean_passes"]
             node_passes = passes32["mean_passes"] * nodes
             flops = FLOPS_PER_NODE_PASS * node_passes + FLOPS_PER_NODE_STEP * nodes
@@ -190,6 +286,13 @@ def main():
             fp32["roofline"] = {"bound": "alu", "achieved": a32, "peak": PEAK_FP32_TFLOPS,
                                 "unit": "TFLOP/s", "frac": a32 / PEAK_FP32_TFLOPS}
         result["fp32_mixed"] = fp32
+
+    if not args.no_adjoint:
+        log("[bench] adjoint / forward")
+        result["adjoint_forward_ratio"] = {
+            "riemann2d_1024_fp64_one_step": adjoint_ratio_1024(cfg64, s64_prev),
+            "compressible_tgv_128_fp32_200_steps_K20": adjoint_ratio_tgv128(),
+        }
 
     if not args.no_cpu_baseline:
         log("[bench] oracle on host cores")

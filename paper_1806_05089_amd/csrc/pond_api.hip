@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -43,6 +44,17 @@ int counters_for_current_device(pond::StepCounters** out) {
   }
   *out = g_counters[dev];
   return POND_OK;
+}
+
+// Passes a node runs one lane per node before an unconverged node moves to the
+// block's 16-lane tail (POND_BULK_CAP overrides the default).
+int bulk_cap(int precision) {
+  static int env = [] {
+    const char* e = getenv("POND_BULK_CAP");
+    return e ? atoi(e) : -1;
+  }();
+  if (env >= 0) return env;
+  return precision == POND_F64 ? 3 : 2;
 }
 
 size_t f_bytes(const pond_config& c) {
@@ -140,6 +152,7 @@ int pond_step(const pond_config* cfg, const pond_state* in, pond_state* out, int
   a.fixed_iter = cfg->fixed_iter;
   a.seed_mode = cfg->seed_mode;
   a.isothermal = cfg->isothermal;
+  a.bulk_cap = bulk_cap(cfg->precision);
   a.tau = cfg->tau;
   a.eps_abs = cfg->eps_abs;
   a.eps_rel = cfg->eps_rel;
@@ -162,6 +175,7 @@ int pond_step(const pond_config* cfg, const pond_state* in, pond_state* out, int
       e = pond::launch_zero_u64(reinterpret_cast<unsigned long long*>(cnt), 4, s);
       if (e != hipSuccess) return hip_fail(e, "pond_step zero counters");
     }
+
     e = pond::launch_step(*cfg, a, s);
     if (e != hipSuccess) return hip_fail(e, "pond_step launch");
     src_f = dst_f;

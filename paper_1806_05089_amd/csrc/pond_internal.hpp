@@ -20,6 +20,9 @@ struct StepArgs {
   int nx, ny;
   int bc_x, bc_y;
   int max_iter, fixed_iter, seed_mode, isothermal;
+  int bulk_cap;  // adaptive mode: passes run one lane per node before the
+                 // block's unconverged nodes move to the 16-lane tail
+                 // (0 or >= max_iter: no tail)
   double tau, eps_abs, eps_rel;
   const void* f_in;
   const double* g_in;

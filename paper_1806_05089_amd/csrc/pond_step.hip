@@ -82,6 +82,261 @@ __device__ __forceinline__ void block_reduce(int v[4], double a[4], int* s_i, do
   }
 }
 
+// Row of G_{B->n} (or any transfer row) rounded to the arithmetic type.
+template <int Q1, class FT>
+__device__ __forceinline__ void row_to(const LagRow& P, double r, double d, FT* out) {
+  double row[Q1];
+  transfer_row_coef<Q1>(P, r, d, row);
+#pragma unroll
+  for (int q = 0; q < Q1; ++q) out[q] = FT(row[q]);
+}
+
+// Speed and Lagrange coefficients for a lane-varying index.
+template <int Q1>
+__device__ __forceinline__ double speed_lane(int i) {
+  double c = Lat<Q1>::c(0);
+#pragma unroll
+  for (int k = 1; k < Q1; ++k) c = i == k ? Lat<Q1>::c(k) : c;
+  return c;
+}
+template <int Q1>
+__device__ __forceinline__ LagRow lag_row_lane(int k) {
+  constexpr LagCoef<Q1> C{};
+  LagRow P{C.v[0][0], C.v[0][1], C.v[0][2], C.v[0][3]};
+#pragma unroll
+  for (int kk = 1; kk < Q1; ++kk) {
+    const bool t = k == kk;
+    P.l0 = t ? C.v[kk][0] : P.l0;
+    P.l1 = t ? C.v[kk][1] : P.l1;
+    P.l2 = t ? C.v[kk][2] : P.l2;
+    P.l3 = t ? C.v[kk][3] : P.l3;
+  }
+  return P;
+}
+
+// a4 for a collocation point read from HBM: the direct transform G_{s->n}
+// with rows Pi, Pj at the node gauge (ux, uy, 1/inv_s).
+template <int Q1, class FT>
+__device__ __forceinline__ FT pair_value_hbm(const StepArgs& A, int gx, int gy, const LagRow& Pi,
+                                             const LagRow& Pj, double ux, double uy, double inv_s) {
+  using L = Lat<Q1>;
+  const size_t plane = (size_t)A.nx * A.ny;
+  const FT* __restrict__ fin = static_cast<const FT*>(A.f_in);
+  const size_t src = (size_t)wrap_index(gy, A.ny, A.bc_y) * A.nx + wrap_index(gx, A.nx, A.bc_x);
+  const double r = sqrt(A.g_in[2 * plane + src] * L::inv_TL) * inv_s;
+  double gxr[Q1], gyr[Q1];
+  transfer_row_coef<Q1>(Pi, r, (A.g_in[src] - ux) * inv_s, gxr);
+  transfer_row_coef<Q1>(Pj, r, (A.g_in[plane + src] - uy) * inv_s, gyr);
+  FT t = FT(0);
+#pragma unroll
+  for (int ip = 0; ip < Q1; ++ip) {
+    FT h = FT(0);
+#pragma unroll
+    for (int jp = 0; jp < Q1; ++jp) h += FT(gyr[jp]) * fin[(size_t)(ip * Q1 + jp) * plane + src];
+    t += FT(gxr[ip]) * h;
+  }
+  return t;
+}
+
+// a4: [G_{lambda_s -> lambda_n} f_s]_(i,j) for the collocation point (gx, gy):
+// G_{B->n} rows (gbx, gby) on the staged window, or the direct transform of
+// the HBM state outside it (rows Pi, Pj at the node gauge (ux, uy, 1/inv_s)).
+template <int Q1, class FT, int WX, int WY, int WN>
+__device__ __forceinline__ FT pair_value(const StepArgs& A, const FT* s_f, int wx0, int wy0, int gx,
+                                         int gy, const FT* gbx, const FT* gby, const LagRow& Pi,
+                                         const LagRow& Pj, double ux, double uy, double inv_s) {
+  using L = Lat<Q1>;
+  const int lx = gx - wx0, ly = gy - wy0;
+  FT t = FT(0);
+  if ((unsigned)lx < (unsigned)WX && (unsigned)ly < (unsigned)WY) {
+    const int k = ly * WX + lx;
+#pragma unroll
+    for (int ip = 0; ip < Q1; ++ip) {
+      FT h = FT(0);
+#pragma unroll
+      for (int jp = 0; jp < Q1; ++jp) h += gby[jp] * s_f[(ip * Q1 + jp) * WN + k];
+      t += gbx[ip] * h;
+    }
+  } else {
+    t = pair_value_hbm<Q1, FT>(A, gx, gy, Pi, Pj, ux, uy, inv_s);
+  }
+  return t;
+}
+
+constexpr int kContinue = 0, kDone = 1, kBad = 2;
+
+// a6 + a7: corrector gauge from the moments of the pass (peculiar frame of
+// the pass gauge (ux, uy, s)) and the App. E test.
+template <int Q1>
+__device__ __forceinline__ int corrector(const StepArgs& A, double s, double ux, double uy, double T,
+                                         double rho, double mx, double my, double e2,
+                                         unsigned passes, double& rho1, double& ux1, double& uy1,
+                                         double& T1, unsigned& flags) {
+  using L = Lat<Q1>;
+  const double dux = s * mx / rho, duy = s * my / rho;
+  rho1 = rho;
+  ux1 = ux + dux;
+  uy1 = uy + duy;
+  T1 = A.isothermal ? T : 0.5 * (s * s * e2 / rho - (dux * dux + duy * duy));
+  if (!(rho1 > 0.0) || !(T1 > 0.0) || !isfinite(rho1) || !isfinite(ux1) || !isfinite(uy1) ||
+      !isfinite(T1))
+    return kBad;
+  if (A.fixed_iter > 0) return (int)passes >= A.fixed_iter ? kDone : kContinue;
+  bool conv = fabs(ux1 - ux) < A.eps_abs + A.eps_rel * fabs(ux1) &&
+              fabs(uy1 - uy) < A.eps_abs + A.eps_rel * fabs(uy1);
+  if (!A.isothermal) {
+    const double s1 = sqrt(T1 * L::inv_TL);
+    conv = conv && fabs(s1 - s) < A.eps_abs + A.eps_rel * fabs(s1);
+  }
+  if (conv) return kDone;
+  if ((int)passes >= A.max_iter) {
+    flags |= POND_ITERS_NONCONVERGED;
+    return kDone;
+  }
+  return kContinue;
+}
+
+// NaN output of a node whose corrector moments were not physical.
+template <int Q1, class FT>
+__device__ __forceinline__ void store_bad(const StepArgs& A, FT* fout, size_t plane, size_t node,
+                                          int p0, int p1) {
+  const double qnan = __builtin_nan("");
+  for (int p = p0; p < p1; ++p) fout[(size_t)p * plane + node] = FT(qnan);
+  if (p0 == 0) {
+    A.g_out[node] = qnan;
+    A.g_out[plane + node] = qnan;
+    A.g_out[2 * plane + node] = qnan;
+  }
+}
+
+// ---- tail: finishing one node with a group of 16 lanes ----
+// Lane p of the group owns population (i, j) = (p / q, p % q).  The group
+// reduces the corrector moments with butterfly shuffles and gathers the
+// populations of the regauge with shuffles.  Every lane of the wave must call
+// this together (the shuffles span the wave); lanes of a group without a node
+// pass has = false.  Collocation points come from the block's LDS window
+// (pair_value, HBM outside it).
+template <int Q1, class FT, int WX, int WY, int WN>
+__device__ __forceinline__ void tail_group(const StepArgs& A, const FT* s_f, int wx0, int wy0,
+                                           double uxB, double uyB, double sB, bool has, int X,
+                                           int Y, double ux, double uy, double T, unsigned passes,
+                                           unsigned long long& c_nc, unsigned long long& c_nb,
+                                           unsigned long long& c_sp, unsigned long long& c_mp) {
+  constexpr int Q = Q1 * Q1;
+  using L = Lat<Q1>;
+  const size_t plane = (size_t)A.nx * A.ny;
+  FT* __restrict__ fout = static_cast<FT*>(A.f_out);
+  const int lane = threadIdx.x & 63, p = lane & 15;
+  const bool pop = p < Q;
+  const int pi = pop ? p / Q1 : 0, pj = pop ? p % Q1 : 0;
+  const double ci = speed_lane<Q1>(pi), cj = speed_lane<Q1>(pj);
+  const LagRow Pi = lag_row_lane<Q1>(pi), Pj = lag_row_lane<Q1>(pj);
+  const int base = lane & ~15;
+  const size_t node = (size_t)Y * A.nx + X;
+  unsigned flags = 0;
+  bool gdone = !has, bad = false;
+  FT fij = FT(0);
+  double rho1 = 0.0, ux1 = ux, uy1 = uy, T1 = T;
+  for (;;) {
+    double s = 0.0;
+    if (!gdone) {
+      ++passes;
+      s = sqrt(T * L::inv_TL);
+      const double inv_s = 1.0 / s;
+      const double rB = sB * inv_s;
+      const double xd = double(X) - (s * ci + ux), yd = double(Y) - (s * cj + uy);
+      const double fl = floor(xd), fly = floor(yd);
+      double ax[4], ay[4];
+      interp_weights(xd - (fl - 1.0), ax);
+      interp_weights(yd - (fly - 1.0), ay);
+      const int x0 = sat_floor(fl) - 1, y0 = sat_floor(fly) - 1;
+      FT gbx[Q1], gby[Q1];
+      row_to<Q1, FT>(Pi, rB, (uxB - ux) * inv_s, gbx);
+      row_to<Q1, FT>(Pj, rB, (uyB - uy) * inv_s, gby);
+      FT acc = FT(0);
+#pragma unroll 1
+      for (int n = 0; n < 4; ++n) {
+        const double axn = n == 0 ? ax[0] : n == 1 ? ax[1] : n == 2 ? ax[2] : ax[3];
+        FT col = FT(0);
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+          col += FT(ay[m]) * pair_value<Q1, FT, WX, WY, WN>(A, s_f, wx0, wy0, x0 + n, y0 + m, gbx,
+                                                            gby, Pi, Pj, ux, uy, inv_s);
+        acc += FT(axn) * col;
+      }
+      fij = pop ? acc : FT(0);
+    }
+    // a6 over the 16 lanes of the group (compensated pairwise sums)
+    const bool live = !gdone && pop;
+    FT v[4] = {live ? fij : FT(0), live ? FT(ci) * fij : FT(0), live ? FT(cj) * fij : FT(0),
+               live ? FT(ci * ci + cj * cj) * fij : FT(0)};
+    FT er[4] = {FT(0), FT(0), FT(0), FT(0)};
+#pragma unroll
+    for (int off = 8; off > 0; off >>= 1) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const FT ov = __shfl_xor(v[k], off), oe = __shfl_xor(er[k], off);
+        const FT t = v[k] + ov;
+        const FT bp = t - v[k];
+        er[k] += oe + ((v[k] - (t - bp)) + (ov - bp));
+        v[k] = t;
+      }
+    }
+    if (!gdone) {
+      const int verdict = corrector<Q1>(A, s, ux, uy, T, double(v[0]) + double(er[0]),
+                                        double(v[1]) + double(er[1]), double(v[2]) + double(er[2]),
+                                        double(v[3]) + double(er[3]), passes, rho1, ux1, uy1, T1,
+                                        flags);
+      if (verdict == kBad) {
+        bad = true;
+        gdone = true;
+      } else if (verdict == kDone) {
+        gdone = true;
+      } else {
+        ux = ux1;
+        uy = uy1;
+        T = T1;
+      }
+    }
+    if (__all(gdone)) break;
+  }
+  // a8 + a9 + a10 for the group's node; every lane joins the shuffles
+  FT fr = FT(0);
+  {
+    const double s = sqrt(T * L::inv_TL), s1 = sqrt(T1 * L::inv_TL);
+    const double inv_s1 = 1.0 / s1, r = s * inv_s1;
+    double ry[Q1], rx[Q1];
+    transfer_row_coef<Q1>(Pj, r, (uy - uy1) * inv_s1, ry);  // row l = pj of Ry
+    transfer_row_coef<Q1>(Pi, r, (ux - ux1) * inv_s1, rx);  // row k = pi of Rx
+    FT h = FT(0);  // Hm(pi, l = pj) = sum_j Ry[l][j] F(pi, j)
+#pragma unroll
+    for (int jj = 0; jj < Q1; ++jj) h += FT(ry[jj]) * __shfl(fij, base + pi * Q1 + jj);
+#pragma unroll
+    for (int ii = 0; ii < Q1; ++ii) fr += FT(rx[ii]) * __shfl(h, base + ii * Q1 + pj);
+  }
+  if (has) {
+    if (bad) {
+      if (pop) store_bad<Q1, FT>(A, fout, plane, node, p, p + 1);
+      flags |= POND_ITERS_BAD;
+    } else if (pop) {
+      const FT feq = FT(rho1 * (L::w(pi) * L::w(pj)));
+      fout[(size_t)p * plane + node] = fr + FT(1.0 / A.tau) * (feq - fr);
+      if (p == 0) {
+        A.g_out[node] = ux1;
+        A.g_out[plane + node] = uy1;
+        A.g_out[2 * plane + node] = T1;
+      }
+    }
+    if (p == 0) {
+      if (A.iters) A.iters[node] = (uint8_t)((passes & POND_ITERS_MASK) | flags);
+      c_nc += (flags & POND_ITERS_NONCONVERGED) ? 1 : 0;
+      c_nb += (flags & POND_ITERS_BAD) ? 1 : 0;
+      c_sp += passes;
+      c_mp = passes > c_mp ? passes : c_mp;
+    }
+  }
+}
+
 template <int Q1, class FT, int TX, int TY, int H>
 __global__ void __launch_bounds__(TX * TY)
 k_step(StepArgs A) {
@@ -92,6 +347,8 @@ k_step(StepArgs A) {
   __shared__ FT s_f[Q * WN];
   __shared__ int s_ri[4 * TS::NW];
   __shared__ double s_rd[4 * TS::NW];
+  __shared__ unsigned s_list[NT];  // deferred nodes: local index | passes << 16
+  __shared__ unsigned s_tail[2];   // list length, next entry to take
 
   // Block -> tile: blocks are dealt to the 8 XCDs round-robin; renumber so
   // that consecutive tiles (which share halo data) run on the same XCD.
@@ -102,6 +359,7 @@ k_step(StepArgs A) {
 
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
+  if (tid < 2) s_tail[tid] = 0u;  // ordered by the barriers below
   const int X = bx0 + (wave % (TX / 8)) * 8 + (lane & 7);
   const int Y = by0 + (wave / (TX / 8)) * 8 + (lane >> 3);
   const bool active = (X < A.nx) && (Y < A.ny);
@@ -205,8 +463,15 @@ k_step(StepArgs A) {
   }
   __syncthreads();
 
+  const bool tail = A.fixed_iter == 0 && A.bulk_cap > 0 && A.bulk_cap < A.max_iter;
+  // step counters of this lane (its own node if finished in the bulk phase,
+  // plus the nodes it finishes as a tail-group leader)
+  unsigned long long c_nc = 0, c_nb = 0, c_sp = 0, c_mp = 0;
+  FT* __restrict__ fout = static_cast<FT*>(A.f_out);
+
   unsigned passes = 0;
   unsigned flags = 0;
+  bool deferred = false;
   if (active) {
     FT ft[Q];
     double ux1 = ux, uy1 = uy, T1 = T, rho1 = 0.0;
@@ -215,7 +480,6 @@ k_step(StepArgs A) {
       ++passes;
       const double s = sqrt(T * L::inv_TL);
       const double inv_s = 1.0 / s;
-      const double uxs = ux * inv_s, uys = uy * inv_s;
       // a4 (window part): G_{B->n} rows are l_k(rB c + dB) per axis.
       const double rB = sB * inv_s;
       const double dBx = (uxB - ux) * inv_s, dBy = (uyB - uy) * inv_s;
@@ -230,15 +494,9 @@ k_step(StepArgs A) {
         double ay[4];
         interp_weights(yd - (fly - 1.0), ay);
         const int y0 = sat_floor(fly) - 1;
-        const int ly0 = y0 - wy0;
         const LagRow Pj = lag_row<Q1>(j);
         FT gby[Q1];
-        {
-          double row[Q1];
-          transfer_row_coef<Q1>(Pj, rB, dBy, row);
-#pragma unroll
-          for (int jp = 0; jp < Q1; ++jp) gby[jp] = FT(row[jp]);
-        }
+        row_to<Q1, FT>(Pj, rB, dBy, gby);
 #pragma unroll 1
         for (int i = 0; i < Q1; ++i) {
           // a2 + a3 (x axis)
@@ -249,57 +507,17 @@ k_step(StepArgs A) {
           const int x0 = sat_floor(fl) - 1;
           const LagRow Pi = lag_row<Q1>(i);
           FT gbx[Q1];
-          {
-            double row[Q1];
-            transfer_row_coef<Q1>(Pi, rB, dBx, row);
-#pragma unroll
-            for (int ip = 0; ip < Q1; ++ip) gbx[ip] = FT(row[ip]);
-          }
+          row_to<Q1, FT>(Pi, rB, dBx, gbx);
           FT acc_ij = FT(0);
 #pragma unroll 1
           for (int n = 0; n < 4; ++n) {
-            const int lx = x0 + n - wx0;
-            const bool in_x = (unsigned)lx < (unsigned)WX;
             const double axn = n == 0 ? ax[0] : n == 1 ? ax[1] : n == 2 ? ax[2] : ax[3];
             FT col = FT(0);
 #pragma unroll
             for (int m = 0; m < 4; ++m) {
-              const int ly = ly0 + m;
-              FT val;
-              if (in_x && (unsigned)ly < (unsigned)WY) {
-                // a4 + a5: [G_{B->n} f^B_s]_(i,j) from the staged window
-                const int k = ly * WX + lx;
-                FT t = FT(0);
-#pragma unroll
-                for (int ip = 0; ip < Q1; ++ip) {
-                  FT h = FT(0);
-#pragma unroll
-                  for (int jp = 0; jp < Q1; ++jp) h += gby[jp] * s_f[(ip * Q1 + jp) * WN + k];
-                  t += gbx[ip] * h;
-                }
-                val = t;
-              } else {
-                // outside the window: [G_{s->n} f_s]_(i,j) from HBM
-                const int sx = wrap_index(x0 + n, A.nx, A.bc_x);
-                const int sy = wrap_index(y0 + m, A.ny, A.bc_y);
-                const size_t src = (size_t)sy * A.nx + sx;
-                const double r = sqrt(gin[2 * plane + src] * L::inv_TL) * inv_s;
-                double gxr[Q1], gyr[Q1];
-                transfer_row_coef<Q1>(Pi, r, fma(gin[src], inv_s, -uxs), gxr);
-                transfer_row_coef<Q1>(Pj, r, fma(gin[plane + src], inv_s, -uys), gyr);
-                FT t = FT(0);
-#pragma unroll
-                for (int ip = 0; ip < Q1; ++ip) {
-                  FT h = FT(0);
-#pragma unroll
-                  for (int jp = 0; jp < Q1; ++jp)
-                    h += FT(gyr[jp]) * fin[(size_t)(ip * Q1 + jp) * plane + src];
-                  t += FT(gxr[ip]) * h;
-                }
-                val = t;
-              }
-              // a5: weight of row m
-              col += FT(ay[m]) * val;
+              const FT val = pair_value<Q1, FT, WX, WY, WN>(A, s_f, wx0, wy0, x0 + n, y0 + m, gbx,
+                                                            gby, Pi, Pj, ux, uy, inv_s);
+              col += FT(ay[m]) * val;  // a5
             }
             acc_ij += FT(axn) * col;
           }
@@ -323,102 +541,125 @@ k_step(StepArgs A) {
           two_sum_acc(my, myc, FT(L::c(j)) * fv);
           two_sum_acc(e2, e2c, FT(L::c(i) * L::c(i) + L::c(j) * L::c(j)) * fv);
         }
-      const double rho = double(r0) + double(r0c);
-      const double dux = s * (double(mx) + double(mxc)) / rho;
-      const double duy = s * (double(my) + double(myc)) / rho;
-      rho1 = rho;
-      ux1 = ux + dux;
-      uy1 = uy + duy;
-      T1 = A.isothermal ? T
-                        : 0.5 * (s * s * (double(e2) + double(e2c)) / rho - (dux * dux + duy * duy));
-      if (!(rho1 > 0.0) || !(T1 > 0.0) || !isfinite(rho1) || !isfinite(ux1) || !isfinite(uy1) ||
-          !isfinite(T1)) {
+      const int verdict = corrector<Q1>(A, s, ux, uy, T, double(r0) + double(r0c),
+                                        double(mx) + double(mxc), double(my) + double(myc),
+                                        double(e2) + double(e2c), passes, rho1, ux1, uy1, T1,
+                                        flags);
+      if (verdict == kBad) {
         bad = true;
         break;
       }
-      bool done;
-      if (A.fixed_iter > 0) {
-        done = (int)passes >= A.fixed_iter;
-      } else {
-        // a7: App. E, each of u_x, u_y, sqrt(theta) separately.
-        bool conv = fabs(ux1 - ux) < A.eps_abs + A.eps_rel * fabs(ux1) &&
-                    fabs(uy1 - uy) < A.eps_abs + A.eps_rel * fabs(uy1);
-        if (!A.isothermal) {
-          const double s1 = sqrt(T1 * L::inv_TL);
-          conv = conv && fabs(s1 - s) < A.eps_abs + A.eps_rel * fabs(s1);
-        }
-        done = conv || (int)passes >= A.max_iter;
-        if (!conv && done) flags |= POND_ITERS_NONCONVERGED;
-      }
-      if (done) break;
+      if (verdict == kDone) break;
       ux = ux1;
       uy = uy1;
       T = T1;
+      if (tail && (int)passes >= A.bulk_cap) {
+        deferred = true;  // continue in the tail with gauge (ux, uy, T)
+        break;
+      }
     }
 
-    FT* __restrict__ fout = static_cast<FT*>(A.f_out);
-    if (bad) {
-      flags |= POND_ITERS_BAD;
-      const double qnan = __builtin_nan("");
+    if (!deferred) {
+      if (bad) {
+        store_bad<Q1, FT>(A, fout, plane, node, 0, Q);
+        flags |= POND_ITERS_BAD;
+      } else {
+        // a8: f^{lambda_n} -> lambda_{n+1}, one full Kronecker transform.
+        const double s = sqrt(T * L::inv_TL), s1 = sqrt(T1 * L::inv_TL);
+        const double inv_s1 = 1.0 / s1, r = s * inv_s1;
+        double Rx[Q], Ry[Q];
+        transfer_factor<Q1, double>(r, (ux - ux1) * inv_s1, Rx);
+        transfer_factor<Q1, double>(r, (uy - uy1) * inv_s1, Ry);
+        FT Hm[Q];  // Hm[i][l] = sum_j Ry[l][j] ft[i][j]
 #pragma unroll
-      for (int p = 0; p < Q; ++p) fout[(size_t)p * plane + node] = FT(qnan);
-      A.g_out[node] = qnan;
-      A.g_out[plane + node] = qnan;
-      A.g_out[2 * plane + node] = qnan;
-    } else {
-      // a8: f^{lambda_n} -> lambda_{n+1}, one full Kronecker transform.
-      const double s = sqrt(T * L::inv_TL), s1 = sqrt(T1 * L::inv_TL);
-      const double inv_s1 = 1.0 / s1, r = s * inv_s1;
-      double Rx[Q], Ry[Q];
-      transfer_factor<Q1, double>(r, (ux - ux1) * inv_s1, Rx);
-      transfer_factor<Q1, double>(r, (uy - uy1) * inv_s1, Ry);
-      FT Hm[Q];  // Hm[i][l] = sum_j Ry[l][j] ft[i][j]
+        for (int i = 0; i < Q1; ++i)
 #pragma unroll
-      for (int i = 0; i < Q1; ++i)
+          for (int l = 0; l < Q1; ++l) {
+            FT h = FT(0);
 #pragma unroll
-        for (int l = 0; l < Q1; ++l) {
-          FT h = FT(0);
+            for (int j = 0; j < Q1; ++j) h += FT(Ry[l * Q1 + j]) * ft[i * Q1 + j];
+            Hm[i * Q1 + l] = h;
+          }
+        // a9: BGK towards rho W (eq. 18), a10: store.
+        const FT omega = FT(1.0 / A.tau);
 #pragma unroll
-          for (int j = 0; j < Q1; ++j) h += FT(Ry[l * Q1 + j]) * ft[i * Q1 + j];
-          Hm[i * Q1 + l] = h;
-        }
-      // a9: BGK towards rho W (eq. 18), a10: store.
-      const FT omega = FT(1.0 / A.tau);
+        for (int k = 0; k < Q1; ++k)
 #pragma unroll
-      for (int k = 0; k < Q1; ++k)
+          for (int l = 0; l < Q1; ++l) {
+            FT fr = FT(0);
 #pragma unroll
-        for (int l = 0; l < Q1; ++l) {
-          FT fr = FT(0);
-#pragma unroll
-          for (int i = 0; i < Q1; ++i) fr += FT(Rx[k * Q1 + i]) * Hm[i * Q1 + l];
-          const FT feq = FT(rho1 * (L::w(k) * L::w(l)));
-          fout[(size_t)(k * Q1 + l) * plane + node] = fr + omega * (feq - fr);
-        }
-      A.g_out[node] = ux1;
-      A.g_out[plane + node] = uy1;
-      A.g_out[2 * plane + node] = T1;
+            for (int i = 0; i < Q1; ++i) fr += FT(Rx[k * Q1 + i]) * Hm[i * Q1 + l];
+            const FT feq = FT(rho1 * (L::w(k) * L::w(l)));
+            fout[(size_t)(k * Q1 + l) * plane + node] = fr + omega * (feq - fr);
+          }
+        A.g_out[node] = ux1;
+        A.g_out[plane + node] = uy1;
+        A.g_out[2 * plane + node] = T1;
+      }
+      if (A.iters) A.iters[node] = (uint8_t)((passes & POND_ITERS_MASK) | flags);
+      c_nc = (flags & POND_ITERS_NONCONVERGED) ? 1 : 0;
+      c_nb = (flags & POND_ITERS_BAD) ? 1 : 0;
+      c_sp = passes;
+      c_mp = passes;
     }
-    if (A.iters) A.iters[node] = (uint8_t)((passes & POND_ITERS_MASK) | flags);
+  }
+
+  // ---- block tail: unconverged nodes, 16 lanes each, all waves of the block ----
+  // A deferred node's next gauge goes through its output gauge slot (read
+  // back with L1-bypassing loads after the barrier); its local index and pass
+  // count go to an LDS list that the block's 16-lane groups drain.
+  if (tail) {
+    if (deferred) {
+      A.g_out[node] = ux;
+      A.g_out[plane + node] = uy;
+      A.g_out[2 * plane + node] = T;
+      const unsigned slot = atomicAdd(&s_tail[0], 1u);
+      s_list[slot] = (unsigned)tid | (passes << 16);
+    }
+    __threadfence_block();
+    __syncthreads();
+    const unsigned count = s_tail[0];
+    if (count) {
+      for (;;) {
+        unsigned e = 0;
+        if ((lane & 15) == 0) e = atomicAdd(&s_tail[1], 1u);
+        e = __shfl(e, lane & ~15);
+        const bool has = e < count;
+        if (__all(!has)) break;
+        const unsigned ent = has ? s_list[e] : 0u;
+        const int ltid = (int)(ent & 0xFFFF);
+        const int lw = ltid >> 6, ll = ltid & 63;
+        const int tX = bx0 + (lw % (TX / 8)) * 8 + (ll & 7);
+        const int tY = by0 + (lw / (TX / 8)) * 8 + (ll >> 3);
+        double tux = 0.0, tuy = 0.0, tT = L::TL;
+        if (has) {
+          const size_t tnode = (size_t)tY * A.nx + tX;
+          tux = __hip_atomic_load(&A.g_out[tnode], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          tuy = __hip_atomic_load(&A.g_out[plane + tnode], __ATOMIC_RELAXED,
+                                  __HIP_MEMORY_SCOPE_AGENT);
+          tT = __hip_atomic_load(&A.g_out[2 * plane + tnode], __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_AGENT);
+        }
+        tail_group<Q1, FT, WX, WY, WN>(A, s_f, wx0, wy0, uxB, uyB, sB, has, tX, tY, tux, tuy, tT,
+                                       ent >> 16, c_nc, c_nb, c_sp, c_mp);
+      }
+    }
   }
 
   if (A.counters) {
-    unsigned long long nc = (flags & POND_ITERS_NONCONVERGED) ? 1ull : 0ull;
-    unsigned long long nb = (flags & POND_ITERS_BAD) ? 1ull : 0ull;
-    unsigned long long sp = passes;
-    unsigned long long mp = passes;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
-      nc += __shfl_xor(nc, off);
-      nb += __shfl_xor(nb, off);
-      sp += __shfl_xor(sp, off);
-      const unsigned long long o = __shfl_xor(mp, off);
-      mp = o > mp ? o : mp;
+      c_nc += __shfl_xor(c_nc, off);
+      c_nb += __shfl_xor(c_nb, off);
+      c_sp += __shfl_xor(c_sp, off);
+      const unsigned long long o = __shfl_xor(c_mp, off);
+      c_mp = o > c_mp ? o : c_mp;
     }
     if (lane == 0) {
-      if (nc) atomicAdd(&A.counters->nonconverged, nc);
-      if (nb) atomicAdd(&A.counters->bad, nb);
-      atomicAdd(&A.counters->sum_passes, sp);
-      atomicMax(&A.counters->max_passes, mp);
+      if (c_nc) atomicAdd(&A.counters->nonconverged, c_nc);
+      if (c_nb) atomicAdd(&A.counters->bad, c_nb);
+      atomicAdd(&A.counters->sum_passes, c_sp);
+      atomicMax(&A.counters->max_passes, c_mp);
     }
   }
 }
