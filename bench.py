@@ -39,7 +39,7 @@ FLOPS_PER_NODE_STEP = 560
 PEAK_FP64_TFLOPS = 78.6   # MI355X vector FP64: 256 CU x 2.4 GHz x 64 lanes x 2
 PEAK_FP32_TFLOPS = 157.3  # MI355X published FP32 peak
 STEP_SOURCE = os.path.join(ROOT, "paper_1806_05089_amd", "csrc", "pond_step.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_riemann2d_1024_fp64_hbm_traffic.json")
 
 
 def log(msg):

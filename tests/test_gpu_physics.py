@@ -1,0 +1,173 @@
+"""Physics of the HIP path at the workloads' full sizes (things the paper fixes).
+
+* Taylor-Green vortex (App. D): second-order convergence of the velocity
+  error at the half-decay time, N = 32, 64, 128.
+* Sod shock tube 1024 x 4, 400 steps: exact gamma = 2 Riemann solution
+  (rarefaction on the exact solution, the shock in the band the oracle pins),
+  FP32-mixed vs FP64 per-field error.
+* Uniform flow at Mach 0..100 stays uniform (one pass per step).
+* Mach 5 Galilean invariance, 256^2, 1000 steps FP32-mixed: the U = (5, 0)
+  run equals the U = 0 run shifted by 5 n nodes.
+* Adjoint rollout on the 128^2 compressible Taylor-Green vortex (Mach 0.5),
+  200 steps, checkpoints every 20: gradients vs central finite differences.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import riemann
+from paper_1806_05089_amd import autograd, pond, workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def _cfg(w, **kw):
+    ny, nx = w.shape
+    base = dict(nx=nx, ny=ny, isothermal=w.isothermal, bc_x=w.bc_x, bc_y=w.bc_y, tau=w.tau)
+    base.update(kw)
+    return pond.PondConfig(**base)
+
+
+def _run(cfg, w, steps):
+    st = pond.init(cfg, w.rho, w.ux, w.uy, w.T)
+    out, stats = pond.step(cfg, st, nsteps=steps, stats=True)
+    return out, stats
+
+
+def test_taylor_green_second_order():
+    errs = []
+    for N in (32, 64, 128):
+        w = workloads.taylor_green(N, mach=0.01, tau=0.6)
+        k = 2 * math.pi / N
+        nu = 1.0 * (0.6 - 0.5)
+        th = int(round(math.log(2.0) / (2 * nu * k * k)))
+        cfg = _cfg(w)
+        out, stats = _run(cfg, w, th)
+        assert stats["bad_state"] == 0 and stats["nonconverged"] == 0
+        _, ux, uy, _ = (a.cpu().numpy() for a in pond.moments(cfg, out))
+        decay = math.exp(-2 * nu * k * k * th)
+        ex, ey = w.ux * decay, w.uy * decay
+        errs.append(math.sqrt(np.sum((ux - ex) ** 2 + (uy - ey) ** 2) / np.sum(ex ** 2 + ey ** 2)))
+        print(f"N={N} t_h={th} rel err {errs[-1]:.3e}", flush=True)
+    order1 = math.log(errs[0] / errs[1]) / math.log(2)
+    order2 = math.log(errs[1] / errs[2]) / math.log(2)
+    assert order1 > 1.7 and order2 > 1.7, (errs, order1, order2)
+
+
+@pytest.mark.parametrize("prec", [pond.POND_F64, pond.POND_F32_MIXED])
+def test_sod_full_size_vs_exact(prec):
+    w = workloads.sod(1024, 4)
+    cfg = _cfg(w, precision=prec)
+    if prec == pond.POND_F32_MIXED:
+        cfg = cfg.replace(eps_abs=1e-6, eps_rel=1e-5)
+    out, stats = _run(cfg, w, 400)
+    assert stats["bad_state"] == 0
+    rho, ux, _, T = (a.cpu().numpy()[0] for a in pond.moments(cfg, out))
+    s = w.meta["scale"]
+    xi = (np.arange(1024) - w.meta["x_diaphragm"]) / 400
+    re, ue, pe = riemann.sample((1.0, 0.0, s), (0.125, 0.0, 0.1 * s), xi)
+    l1 = [np.mean(np.abs(rho - re)), np.mean(np.abs(ux - ue)), np.mean(np.abs(rho * T - pe))]
+    print(f"prec {prec} L1 rho {l1[0]:.3e} u {l1[1]:.3e} p {l1[2]:.3e}", flush=True)
+    assert l1[0] < 0.008 and l1[1] < 0.016 and l1[2] < 0.003
+    assert abs(np.min(np.nonzero(rho < 0.9)[0]) - np.min(np.nonzero(re < 0.9)[0])) <= 1
+    _, _, _, shock = riemann.wave_speeds((1.0, 0.0, s), (0.125, 0.0, 0.1 * s))
+    xs = w.meta["x_diaphragm"] + shock * 400
+    sim = np.max(np.nonzero(rho > 0.5 * (0.125 + 0.2043))[0])
+    assert -0.08 * shock * 400 < sim - xs < 0.0
+
+
+def test_sod_fp32_vs_fp64_error():
+    w = workloads.sod(1024, 4)
+    c64 = _cfg(w)
+    c32 = _cfg(w, precision=pond.POND_F32_MIXED, eps_abs=1e-6, eps_rel=1e-5)
+    o64, _ = _run(c64, w, 400)
+    o32, _ = _run(c32, w, 400)
+    m64 = [a.cpu().numpy() for a in pond.moments(c64, o64)]
+    m32 = [a.cpu().numpy() for a in pond.moments(c32, o32)]
+    e = {n: float(np.max(np.abs(a - b)) / max(1.0, np.max(np.abs(b))))
+         for n, a, b in zip(("rho", "ux", "uy", "T"), m32, m64)}
+    print("Sod FP32-mixed vs FP64 max rel:", e, flush=True)
+    assert e["rho"] < 5e-3 and e["ux"] < 5e-3 and e["T"] < 5e-3
+
+
+@pytest.mark.parametrize("U,T", [(0.0, 1.0), (5.0, 1.0), (30.0, 0.5), (100.0, 2.0)])
+def test_uniform_flow_any_mach(U, T):
+    w = workloads.uniform(64, 48, rho=1.3, ux=U, uy=-0.3 * U, T=T)
+    cfg = _cfg(w)
+    st = pond.init(cfg, w.rho, w.ux, w.uy, w.T)
+    out, stats = pond.step(cfg, st.clone(), nsteps=10, stats=True)
+    assert stats["max_iters"] == 1 and stats["nonconverged"] == 0
+    assert torch.max(torch.abs(out.f - st.f)).item() < 1e-12
+    assert torch.max(torch.abs(out.g[:2] - st.g[:2])).item() < 1e-13 * max(1.0, U)
+
+
+def test_mach5_galilean_1000_steps_fp32():
+    N, steps = 256, 1000
+    w0 = workloads.mach5(N, U=0.0, seed=0)
+    wU = workloads.mach5(N, U=5.0, seed=0)
+    res = {}
+    for prec in (pond.POND_F32_MIXED, pond.POND_F64):
+        kw = dict(precision=prec)
+        if prec == pond.POND_F32_MIXED:
+            kw.update(eps_abs=1e-6, eps_rel=1e-5)
+        c = _cfg(w0, **kw)
+        o0, s0 = _run(c, w0, steps)
+        oU, sU = _run(c, wU, steps)
+        r0 = pond.moments(c, o0)[0].cpu().numpy()
+        rU = pond.moments(c, oU)[0].cpu().numpy()
+        shifted = np.roll(r0, (5 * steps) % N, axis=1)
+        res[prec] = float(np.max(np.abs(rU - shifted))) / 1e-3
+        print(f"prec {prec}: Galilean error / perturbation = {res[prec]:.3e}, passes "
+              f"{s0['mean_iters']:.2f} / {sU['mean_iters']:.2f}", flush=True)
+    assert res[pond.POND_F64] < 1e-6
+    assert res[pond.POND_F32_MIXED] < 2e-2
+
+
+def test_adjoint_rollout_128_vs_finite_differences():
+    w = workloads.compressible_taylor_green(128, seed=1)
+    nsteps, K = 200, 20
+    dev = torch.device("cuda")
+    rng = np.random.default_rng(2)
+    d = rng.standard_normal(w.ux.shape)
+    results = {}
+    for prec in (pond.POND_F64, pond.POND_F32_MIXED):
+        cfg = pond.PondConfig(nx=128, ny=128, precision=prec, tau=0.6, fixed_iter=3)
+        ux = torch.tensor(w.ux, dtype=torch.float64, device=dev, requires_grad=True)
+        tau = torch.tensor(0.6, dtype=torch.float64, device=dev, requires_grad=True)
+        f0, g0 = autograd.equilibrium_state(cfg, torch.tensor(w.rho, device=dev), ux,
+                                            torch.tensor(w.uy, device=dev),
+                                            torch.tensor(w.T, device=dev))
+        fT, gT = autograd.rollout(f0, g0, tau, cfg, nsteps, checkpoint_every=K)
+        J = autograd.kinetic_energy(fT, gT)
+        J.backward()
+        results[prec] = (float(np.sum(ux.grad.cpu().numpy() * d)), float(tau.grad.item()))
+
+    # central differences (h = 1e-4) of the FP64 forward
+    h = 1e-4
+    c64 = pond.PondConfig(nx=128, ny=128, tau=0.6, fixed_iter=3)
+
+    def J_of(ux_np, tau_v):
+        c = c64.replace(tau=tau_v)
+        st = pond.init(c, w.rho, ux_np, w.uy, w.T)
+        out, _ = pond.step(c, st, nsteps=nsteps)
+        return float(autograd.kinetic_energy(out.f, out.g).item())
+
+    fd_u = (J_of(w.ux + h * d, 0.6) - J_of(w.ux - h * d, 0.6)) / (2 * h)
+    fd_t = (J_of(w.ux, 0.6 + h) - J_of(w.ux, 0.6 - h)) / (2 * h)
+    # the computed map is piecewise smooth (stencil origins floor(x - v) switch
+    # under a finite perturbation), so central differences carry O(h) kinks on
+    # top of O(h^2); halving h must move them towards the adjoint
+    fd_u2 = (J_of(w.ux + 0.5 * h * d, 0.6) - J_of(w.ux - 0.5 * h * d, 0.6)) / h
+    print(f"dJ.d: adjoint64 {results[pond.POND_F64][0]:.8e} adjoint32 "
+          f"{results[pond.POND_F32_MIXED][0]:.8e} FD {fd_u:.8e}", flush=True)
+    print(f"dJ/dtau: adjoint64 {results[pond.POND_F64][1]:.8e} adjoint32 "
+          f"{results[pond.POND_F32_MIXED][1]:.8e} FD {fd_t:.8e}", flush=True)
+    print(f"dJ.d: FD(h/2) {fd_u2:.8e}", flush=True)
+    adj = results[pond.POND_F64][0]
+    assert abs(adj - fd_u) <= 1e-5 * abs(fd_u)
+    assert abs(adj - fd_u2) < abs(adj - fd_u)
+    assert abs(results[pond.POND_F64][1] - fd_t) <= 1e-6 * abs(fd_t)
+    assert abs(results[pond.POND_F32_MIXED][0] - fd_u) <= 1e-3 * abs(fd_u)
+    assert abs(results[pond.POND_F32_MIXED][1] - fd_t) <= 1e-3 * abs(fd_t)
