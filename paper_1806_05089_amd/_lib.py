@@ -1,4 +1,6 @@
 """ctypes declarations of libpond's C ABI (include/pond.h).  Marshalling only."""
+from __future__ import annotations
+
 import ctypes as C
 import os
 
@@ -52,11 +54,14 @@ class PondError(RuntimeError):
 _lib = None
 
 
-def load(path: str = LIB_PATH):
-    """Load libpond.so (built in-tree by paper_1806_05089_amd.build).  No fallback."""
+def load(path: str | None = None):
+    """Load libpond.so (built in-tree by paper_1806_05089_amd.build, or the file
+    named by POND_LIBRARY).  No fallback."""
     global _lib
     if _lib is not None:
         return _lib
+    if path is None:
+        path = os.environ.get("POND_LIBRARY", LIB_PATH)
     if not os.path.exists(path):
         raise ImportError(f"libpond.so not found at {path}; build it with "
                           "`python -m paper_1806_05089_amd.build` (no CPU fallback exists)")

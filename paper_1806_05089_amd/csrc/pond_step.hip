@@ -124,6 +124,9 @@ __device__ __forceinline__ FT pair_value_hbm(const StepArgs& A, int gx, int gy, 
   const FT* __restrict__ fin = static_cast<const FT*>(A.f_in);
   const size_t src = (size_t)wrap_index(gy, A.ny, A.bc_y) * A.nx + wrap_index(gx, A.nx, A.bc_x);
   const double r = sqrt(A.g_in[2 * plane + src] * L::inv_TL) * inv_s;
+  FT f[Q1 * Q1];
+#pragma unroll
+  for (int p = 0; p < Q1 * Q1; ++p) f[p] = fin[(size_t)p * plane + src];
   double gxr[Q1], gyr[Q1];
   transfer_row_coef<Q1>(Pi, r, (A.g_in[src] - ux) * inv_s, gxr);
   transfer_row_coef<Q1>(Pj, r, (A.g_in[plane + src] - uy) * inv_s, gyr);
@@ -132,7 +135,7 @@ __device__ __forceinline__ FT pair_value_hbm(const StepArgs& A, int gx, int gy, 
   for (int ip = 0; ip < Q1; ++ip) {
     FT h = FT(0);
 #pragma unroll
-    for (int jp = 0; jp < Q1; ++jp) h += FT(gyr[jp]) * fin[(size_t)(ip * Q1 + jp) * plane + src];
+    for (int jp = 0; jp < Q1; ++jp) h += FT(gyr[jp]) * f[ip * Q1 + jp];
     t += FT(gxr[ip]) * h;
   }
   return t;
@@ -150,17 +153,103 @@ __device__ __forceinline__ FT pair_value(const StepArgs& A, const FT* s_f, int w
   FT t = FT(0);
   if ((unsigned)lx < (unsigned)WX && (unsigned)ly < (unsigned)WY) {
     const int k = ly * WX + lx;
+    FT f[Q1 * Q1];
+#pragma unroll
+    for (int p = 0; p < Q1 * Q1; ++p) f[p] = s_f[p * WN + k];
 #pragma unroll
     for (int ip = 0; ip < Q1; ++ip) {
       FT h = FT(0);
 #pragma unroll
-      for (int jp = 0; jp < Q1; ++jp) h += gby[jp] * s_f[(ip * Q1 + jp) * WN + k];
+      for (int jp = 0; jp < Q1; ++jp) h += gby[jp] * f[ip * Q1 + jp];
       t += gbx[ip] * h;
     }
   } else {
     t = pair_value_hbm<Q1, FT>(A, gx, gy, Pi, Pj, ux, uy, inv_s);
   }
   return t;
+}
+
+// Wave-wide minimum / maximum of an int.
+__device__ __forceinline__ int wave_min(int v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const int o = __shfl_xor(v, off);
+    v = o < v ? o : v;
+  }
+  return v;
+}
+__device__ __forceinline__ int wave_max(int v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const int o = __shfl_xor(v, off);
+    v = o > v ? o : v;
+  }
+  return v;
+}
+
+// a4 for one collocation point (gx, gy) and every x speed i:
+// t[i] = [G_{lambda_s -> lambda_n} f_s]_(i,j).  On the LDS window the y
+// contraction with the G_{B->n} row gby is done once and shared; outside it
+// the point is read from HBM and transformed directly (rows of G_{s->n}).
+template <int Q1, class FT, int WX, int WY, int WN>
+__device__ __forceinline__ void column_values(const StepArgs& A, const FT* s_f, int wx0, int wy0,
+                                              int gx, int gy, bool need, const FT (&gbx)[Q1][Q1],
+                                              const FT* gby, const LagRow& Pj, double ux,
+                                              double uy, double inv_s, FT* t) {
+  using L = Lat<Q1>;
+#pragma unroll
+  for (int i = 0; i < Q1; ++i) t[i] = FT(0);
+  const int lx = gx - wx0, ly = gy - wy0;
+  if (need && (unsigned)lx < (unsigned)WX && (unsigned)ly < (unsigned)WY) {
+    const int k = ly * WX + lx;
+    // all Q loads first, so that they are in flight together
+    FT f[Q1 * Q1];
+#pragma unroll
+    for (int p = 0; p < Q1 * Q1; ++p) f[p] = s_f[p * WN + k];
+    FT h[Q1];
+#pragma unroll
+    for (int ip = 0; ip < Q1; ++ip) {
+      FT v = FT(0);
+#pragma unroll
+      for (int jp = 0; jp < Q1; ++jp) v += gby[jp] * f[ip * Q1 + jp];
+      h[ip] = v;
+    }
+#pragma unroll
+    for (int i = 0; i < Q1; ++i) {
+      FT v = FT(0);
+#pragma unroll
+      for (int ip = 0; ip < Q1; ++ip) v += gbx[i][ip] * h[ip];
+      t[i] = v;
+    }
+  } else if (need) {
+    const size_t plane = (size_t)A.nx * A.ny;
+    const FT* __restrict__ fin = static_cast<const FT*>(A.f_in);
+    const size_t src = (size_t)wrap_index(gy, A.ny, A.bc_y) * A.nx + wrap_index(gx, A.nx, A.bc_x);
+    FT f[Q1 * Q1];
+#pragma unroll
+    for (int p = 0; p < Q1 * Q1; ++p) f[p] = fin[(size_t)p * plane + src];
+    const double r = sqrt(A.g_in[2 * plane + src] * L::inv_TL) * inv_s;
+    const double dx = (A.g_in[src] - ux) * inv_s;
+    double gyr[Q1];
+    transfer_row_coef<Q1>(Pj, r, (A.g_in[plane + src] - uy) * inv_s, gyr);
+    FT h[Q1];
+#pragma unroll
+    for (int ip = 0; ip < Q1; ++ip) {
+      FT v = FT(0);
+#pragma unroll
+      for (int jp = 0; jp < Q1; ++jp) v += FT(gyr[jp]) * f[ip * Q1 + jp];
+      h[ip] = v;
+    }
+#pragma unroll
+    for (int i = 0; i < Q1; ++i) {
+      double gxr[Q1];
+      transfer_row<Q1>(i, r, dx, gxr);
+      FT v = FT(0);
+#pragma unroll
+      for (int ip = 0; ip < Q1; ++ip) v += FT(gxr[ip]) * h[ip];
+      t[i] = v;
+    }
+  }
 }
 
 constexpr int kContinue = 0, kDone = 1, kBad = 2;
@@ -484,8 +573,33 @@ k_step(StepArgs A) {
       const double rB = sB * inv_s;
       const double dBx = (uxB - ux) * inv_s, dBy = (uyB - uy) * inv_s;
 
-      // (y speed j, x speed i, stencil column n) are wave-uniform rolled
-      // loops; the four stencil rows of one column are unrolled.
+      // a2 + a3 (x axis) for every x speed: departure columns x0_i (as offsets
+      // o_i = x0_i - X), weights, and the rows of G_{B->n} along x.
+      int o[Q1];
+      double ax[Q1][4];
+      FT gbx[Q1][Q1];
+      int lo = INT_MAX, hi = INT_MIN;
+#pragma unroll
+      for (int i = 0; i < Q1; ++i) {
+        const double xd = double(X) - (s * L::c(i) + ux);
+        const double fl = floor(xd);
+        interp_weights(xd - (fl - 1.0), ax[i]);
+        o[i] = sat_floor(fl) - 1 - X;
+        double row[Q1];
+        transfer_row<Q1>(i, rB, dBx, row);
+#pragma unroll
+        for (int ip = 0; ip < Q1; ++ip) gbx[i][ip] = FT(row[ip]);
+        if (isfinite(xd)) {
+          lo = o[i] < lo ? o[i] : lo;
+          hi = o[i] + 3 > hi ? o[i] + 3 : hi;
+        }
+      }
+      // The wave walks the union of its lanes' stencil columns once per y
+      // speed; every collocation point of a column is read from LDS once and
+      // its y contraction is shared by the four x speeds (each with its own
+      // weight, zero where the column is outside that speed's stencil).
+      lo = wave_min(lo);
+      hi = wave_max(hi);
 #pragma unroll 1
       for (int j = 0; j < Q1; ++j) {
         // a2 + a3 (y axis): the departure ordinate depends on c_j only.
@@ -497,36 +611,37 @@ k_step(StepArgs A) {
         const LagRow Pj = lag_row<Q1>(j);
         FT gby[Q1];
         row_to<Q1, FT>(Pj, rB, dBy, gby);
-#pragma unroll 1
-        for (int i = 0; i < Q1; ++i) {
-          // a2 + a3 (x axis)
-          const double xd = double(X) - (s * speed_rt<Q1>(i) + ux);
-          const double fl = floor(xd);
-          double ax[4];
-          interp_weights(xd - (fl - 1.0), ax);
-          const int x0 = sat_floor(fl) - 1;
-          const LagRow Pi = lag_row<Q1>(i);
-          FT gbx[Q1];
-          row_to<Q1, FT>(Pi, rB, dBx, gbx);
-          FT acc_ij = FT(0);
-#pragma unroll 1
-          for (int n = 0; n < 4; ++n) {
-            const double axn = n == 0 ? ax[0] : n == 1 ? ax[1] : n == 2 ? ax[2] : ax[3];
-            FT col = FT(0);
+        FT acc_row[Q1];
 #pragma unroll
-            for (int m = 0; m < 4; ++m) {
-              const FT val = pair_value<Q1, FT, WX, WY, WN>(A, s_f, wx0, wy0, x0 + n, y0 + m, gbx,
-                                                            gby, Pi, Pj, ux, uy, inv_s);
-              col += FT(ay[m]) * val;  // a5
-            }
-            acc_ij += FT(axn) * col;
+        for (int i = 0; i < Q1; ++i) acc_row[i] = FT(0);
+#pragma unroll 1
+        for (int rel = lo; rel <= hi; ++rel) {
+          FT wx[Q1];
+          bool need = false;
+#pragma unroll
+          for (int i = 0; i < Q1; ++i) {
+            const int n = rel - o[i];
+            const bool in = (unsigned)n < 4u;
+            const double a = n == 0 ? ax[i][0] : n == 1 ? ax[i][1] : n == 2 ? ax[i][2] : ax[i][3];
+            wx[i] = in ? FT(a) : FT(0);
+            need = need || in;
           }
+          if (!__any(need)) continue;
+#pragma unroll 2
+          for (int m = 0; m < 4; ++m) {
+            FT t[Q1];
+            column_values<Q1, FT, WX, WY, WN>(A, s_f, wx0, wy0, X + rel, y0 + m, need, gbx, gby,
+                                              Pj, ux, uy, inv_s, t);
+            const FT aym = FT(m == 0 ? ay[0] : m == 1 ? ay[1] : m == 2 ? ay[2] : ay[3]);
 #pragma unroll
-          for (int ii = 0; ii < Q1; ++ii)
-#pragma unroll
-            for (int jj = 0; jj < Q1; ++jj)
-              if (ii == i && jj == j) ft[ii * Q1 + jj] = acc_ij;
+            for (int i = 0; i < Q1; ++i) acc_row[i] += (wx[i] * aym) * t[i];  // a5
+          }
         }
+#pragma unroll
+        for (int i = 0; i < Q1; ++i)
+#pragma unroll
+          for (int jj = 0; jj < Q1; ++jj)
+            if (jj == j) ft[i * Q1 + jj] = acc_row[i];
       }
 
       // a6: moments in the peculiar frame of lambda_n (compensated sums).

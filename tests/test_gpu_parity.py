@@ -77,6 +77,9 @@ CASES_ADAPTIVE = [
     ("tgv32_isothermal", lambda: workloads.taylor_green(32), 4),
     ("sod_128x2", lambda: workloads.sod(128, 2), 4),
     ("d2q9_smooth", lambda: workloads.random_smooth(40, 36, seed=5, T0=1.0 / 3.0, mach=0.2), 3),
+    # sharp quadrant interfaces: nodes needing 6..20 passes finish in the
+    # block's 16-lane tail
+    ("riemann2d_64", lambda: workloads.riemann2d(64, seed=3), 4),
 ]
 
 
@@ -93,6 +96,22 @@ def test_step_fp64_adaptive(gpu, name, make, q):
     assert max(errs.values()) < 1e-9, errs
     if same.all():
         assert max(errs.values()) < TOL64, errs
+
+
+def test_adaptive_tail_runs_and_counts(gpu):
+    """The Riemann interfaces need up to max_iter passes at t = 0: the step
+    statistics must count them as the oracle does."""
+    w = workloads.riemann2d(64, seed=3)
+    cfg = _cfg(w, max_iter=20)
+    st = pond.init(cfg, w.rho, w.ux, w.uy, w.T)
+    out, stats = pond.step(cfg, st, stats=True)
+    f0, g0 = oracle.init(w.rho, w.ux, w.uy, w.T, q=4)
+    _, _, io, _ = oracle.step(f0, g0, _ocfg(cfg))
+    ig = out.iters.cpu().numpy()
+    assert stats["max_iters"] == int(np.max(io & pond.POND_ITERS_MASK)) == 20
+    assert np.sum(ig & pond.POND_ITERS_MASK > 8) > 100
+    assert stats["nonconverged"] == int(np.sum((ig & pond.POND_ITERS_NONCONVERGED) != 0))
+    assert abs(stats["mean_iters"] - float(np.mean(ig & pond.POND_ITERS_MASK))) < 1e-12
 
 
 @pytest.mark.parametrize("nsteps", [1, 2, 5])
