@@ -4,7 +4,9 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <mutex>
+#include <utility>
 #include <string>
 
 #include "pond.h"
@@ -23,26 +25,66 @@ int hip_fail(hipError_t e, const char* where) {
   return fail(POND_E_HIP, std::string(where) + ": " + hipGetErrorString(e));
 }
 
-// Small per-device buffer for step counters, allocated on first use and held
-// until the process ends.
-constexpr int kMaxDevices = 64;
+// Device memory kept per (device, stream): step statistics, the step
+// kernel's tile queue, and the tile cost keys and tile order that one step
+// leaves for the next.  Work on one stream runs in order, so a slot is never
+// used by two kernels at once.  Allocated on the first call on a stream (the
+// tile arrays grow with the grid) and held until the process ends.
+struct Slot {
+  pond::StreamSlot* dev = nullptr;
+  uint16_t* keys = nullptr;
+  unsigned* order = nullptr;
+  size_t cap = 0;           // tiles the arrays hold
+  int order_nx = -1;        // grid whose tile order `order` holds
+  int order_ny = -1;
+};
 std::mutex g_mutex;
-pond::StepCounters* g_counters[kMaxDevices] = {nullptr};
+std::map<std::pair<int, void*>, Slot> g_slots;
 
-int counters_for_current_device(pond::StepCounters** out) {
+int slot_for_stream(hipStream_t s, Slot** out) {
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
-  if (dev < 0 || dev >= kMaxDevices) return fail(POND_E_UNSUPPORTED, "device index too large");
   std::lock_guard<std::mutex> lock(g_mutex);
-  if (!g_counters[dev]) {
-    e = hipMalloc(reinterpret_cast<void**>(&g_counters[dev]), sizeof(pond::StepCounters));
+  Slot& sl = g_slots[std::make_pair(dev, static_cast<void*>(s))];
+  if (!sl.dev) {
+    pond::StreamSlot* p = nullptr;
+    e = hipMalloc(reinterpret_cast<void**>(&p), sizeof(pond::StreamSlot));
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc(stream slot)");
+    e = hipMemset(p, 0, sizeof(pond::StreamSlot));
     if (e != hipSuccess) {
-      g_counters[dev] = nullptr;
-      return hip_fail(e, "hipMalloc(counters)");
+      (void)hipFree(p);
+      return hip_fail(e, "hipMemset(stream slot)");
     }
+    sl.dev = p;
   }
-  *out = g_counters[dev];
+  *out = &sl;
+  return POND_OK;
+}
+
+// Tile key and order arrays for `ntiles` tiles.  Growing them waits for the
+// stream, since a kernel in flight may still use the old arrays.
+int ensure_tile_arrays(Slot* sl, size_t ntiles, hipStream_t s) {
+  if (sl->cap >= ntiles) return POND_OK;
+  hipError_t e;
+  if (sl->cap) {
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "pond_step sync");
+    (void)hipFree(sl->keys);
+    (void)hipFree(sl->order);
+    sl->keys = nullptr;
+    sl->order = nullptr;
+    sl->cap = 0;
+  }
+  sl->order_nx = sl->order_ny = -1;
+  e = hipMalloc(reinterpret_cast<void**>(&sl->keys), ntiles * sizeof(uint16_t));
+  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&sl->order), ntiles * sizeof(unsigned));
+  if (e != hipSuccess) {
+    (void)hipFree(sl->keys);
+    sl->keys = nullptr;
+    sl->order = nullptr;
+    return hip_fail(e, "hipMalloc(tile arrays)");
+  }
+  sl->cap = ntiles;
   return POND_OK;
 }
 
@@ -108,8 +150,9 @@ int pond_init(const pond_config* cfg, const double* rho, const double* ux, const
   if (!rho || !ux || !uy || !T) return fail(POND_E_NULL, "pond_init: a field pointer is NULL");
   if (!out || !out->f || !out->g) return fail(POND_E_NULL, "pond_init: output state is NULL");
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
-  pond::StepCounters* cnt = nullptr;
-  if ((rc = counters_for_current_device(&cnt))) return rc;
+  Slot* slot = nullptr;
+  if ((rc = slot_for_stream(s, &slot))) return rc;
+  pond::StepCounters* cnt = &slot->dev->counters;
   hipError_t e = pond::launch_zero_u64(&cnt->bad, 1, s);
   if (e != hipSuccess) return hip_fail(e, "pond_init zero");
   e = pond::launch_init(*cfg, rho, ux, uy, T, out->f, out->g, out->iters, &cnt->bad, s);
@@ -140,8 +183,10 @@ int pond_step(const pond_config* cfg, const pond_state* in, pond_state* out, int
       overlap(in->f, fb, out->g, gb) || overlap(in->g, gb, out->f, fb))
     return fail(POND_E_ALIAS, "pond_step: input and output state overlap");
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
-  pond::StepCounters* cnt = nullptr;
-  if (stats && (rc = counters_for_current_device(&cnt))) return rc;
+  Slot* slot = nullptr;
+  if ((rc = slot_for_stream(s, &slot))) return rc;
+  pond::StepCounters* cnt = stats ? &slot->dev->counters : nullptr;
+  if ((rc = ensure_tile_arrays(slot, pond::step_tile_count(*cfg), s))) return rc;
 
   pond::StepArgs a;
   a.nx = cfg->nx;
@@ -157,6 +202,9 @@ int pond_step(const pond_config* cfg, const pond_state* in, pond_state* out, int
   a.eps_abs = cfg->eps_abs;
   a.eps_rel = cfg->eps_rel;
   a.iters = out->iters;
+  a.queue = &slot->dev->queue;
+  a.tile_keys = slot->keys;
+  a.tile_order_next = slot->order;
 
   const void* src_f = in->f;
   const double* src_g = in->g;
@@ -171,13 +219,21 @@ int pond_step(const pond_config* cfg, const pond_state* in, pond_state* out, int
     a.f_out = dst_f;
     a.g_out = dst_g;
     a.counters = (last && cnt) ? cnt : nullptr;
+    // the previous step on this stream left a tile order for this grid
+    const bool ordered = slot->order_nx == cfg->nx && slot->order_ny == cfg->ny;
+    a.tile_order = ordered ? slot->order : nullptr;
     if (a.counters) {
       e = pond::launch_zero_u64(reinterpret_cast<unsigned long long*>(cnt), 4, s);
       if (e != hipSuccess) return hip_fail(e, "pond_step zero counters");
     }
 
     e = pond::launch_step(*cfg, a, s);
-    if (e != hipSuccess) return hip_fail(e, "pond_step launch");
+    if (e != hipSuccess) {
+      slot->order_nx = slot->order_ny = -1;
+      return hip_fail(e, "pond_step launch");
+    }
+    slot->order_nx = cfg->nx;
+    slot->order_ny = cfg->ny;
     src_f = dst_f;
     src_g = dst_g;
   }

@@ -16,6 +16,21 @@ struct StepCounters {
   unsigned long long max_passes;
 };
 
+// Tile queue of the persistent step kernel: blocks take tiles in order from
+// `next`; the last block to finish resets both fields to zero, so the queue is
+// ready for the next launch on the same stream.
+struct TileQueue {
+  unsigned next;
+  unsigned done;
+};
+
+// Device memory the library keeps per (device, stream): the step statistics
+// and the tile queue.  Zeroed once when allocated.
+struct StreamSlot {
+  StepCounters counters;
+  TileQueue queue;
+};
+
 struct StepArgs {
   int nx, ny;
   int bc_x, bc_y;
@@ -30,12 +45,21 @@ struct StepArgs {
   double* g_out;
   uint8_t* iters;
   StepCounters* counters;  // nullable
+  TileQueue* queue;
+  // Tile order: tiles are taken in the order tile_order[0..ntiles) (nullable:
+  // row-major).  Each tile writes its cost key to tile_keys (nullable), and the
+  // last block writes the order for the next step, costliest first, to
+  // tile_order_next (nullable; may equal tile_order).
+  uint16_t* tile_keys;
+  const unsigned* tile_order;
+  unsigned* tile_order_next;
 };
 
 hipError_t launch_init(const pond_config& c, const double* rho, const double* ux,
                        const double* uy, const double* T, void* f, double* g, uint8_t* iters,
                        unsigned long long* bad_count, hipStream_t s);
 hipError_t launch_step(const pond_config& c, const StepArgs& a, hipStream_t s);
+unsigned step_tile_count(const pond_config& c);
 hipError_t launch_moments(const pond_config& c, const void* f, const double* g, double* rho,
                           double* ux, double* uy, double* T, double* Mmn, hipStream_t s);
 hipError_t launch_zero_u64(unsigned long long* p, int n, hipStream_t s);

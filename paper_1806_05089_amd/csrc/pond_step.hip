@@ -304,18 +304,25 @@ __device__ __forceinline__ void store_bad(const StepArgs& A, FT* fout, size_t pl
 // populations of the regauge with shuffles.  Every lane of the wave must call
 // this together (the shuffles span the wave); lanes of a group without a node
 // pass has = false.  Collocation points come from the block's LDS window
-// (pair_value, HBM outside it).
+// (pair_value, HBM outside it).  The group's final pass count raises *s_key,
+// the pass maximum of the wave that deferred the node.
 template <int Q1, class FT, int WX, int WY, int WN>
 __device__ __forceinline__ void tail_group(const StepArgs& A, const FT* s_f, int wx0, int wy0,
                                            double uxB, double uyB, double sB, bool has, int X,
                                            int Y, double ux, double uy, double T, unsigned passes,
-                                           unsigned long long& c_nc, unsigned long long& c_nb,
-                                           unsigned long long& c_sp, unsigned long long& c_mp) {
+                                           unsigned* s_key, unsigned long long& c_nc,
+                                           unsigned long long& c_nb, unsigned long long& c_sp,
+                                           unsigned long long& c_mp) {
   constexpr int Q = Q1 * Q1;
   using L = Lat<Q1>;
   const size_t plane = (size_t)A.nx * A.ny;
   FT* __restrict__ fout = static_cast<FT*>(A.f_out);
-  const int lane = threadIdx.x & 63, p = lane & 15;
+  int lane = threadIdx.x & 63;
+  // Opaque to the optimiser: keeps the per-lane rows below from being hoisted
+  // out of the block's tile loop (where they would stay live through the bulk
+  // passes and cost registers).
+  asm volatile("" : "+v"(lane));
+  const int p = lane & 15;
   const bool pop = p < Q;
   const int pi = pop ? p / Q1 : 0, pj = pop ? p % Q1 : 0;
   const double ci = speed_lane<Q1>(pi), cj = speed_lane<Q1>(pj);
@@ -418,12 +425,45 @@ __device__ __forceinline__ void tail_group(const StepArgs& A, const FT* s_f, int
     }
     if (p == 0) {
       if (A.iters) A.iters[node] = (uint8_t)((passes & POND_ITERS_MASK) | flags);
+      atomicMax(s_key, passes);
       c_nc += (flags & POND_ITERS_NONCONVERGED) ? 1 : 0;
       c_nb += (flags & POND_ITERS_BAD) ? 1 : 0;
       c_sp += passes;
       c_mp = passes > c_mp ? passes : c_mp;
     }
   }
+}
+
+// Tile cost keys: the sum over the tile's waves of the most passes a node of
+// the wave took (at most 8 waves x 63 passes).
+constexpr unsigned kKeyBins = 512;
+
+// Counting sort of the tiles by key, largest first, into order[] (one block,
+// NT threads, 3 kKeyBins words of LDS).  Tiles with equal keys land in any
+// order; the step's results do not depend on the order of its tiles.
+template <int NT>
+__device__ void order_tiles(const uint16_t* keys, unsigned* order, unsigned ntiles,
+                            unsigned* lds) {
+  static_assert(NT >= (int)kKeyBins, "one thread per key bin");
+  unsigned* hist = lds;
+  unsigned* scan = lds + kKeyBins;
+  unsigned* start = lds + 2 * kKeyBins;
+  const int tid = threadIdx.x;
+  if (tid < (int)kKeyBins) hist[tid] = 0u;
+  __syncthreads();
+  for (unsigned t = tid; t < ntiles; t += NT) atomicAdd(&hist[keys[t]], 1u);
+  __syncthreads();
+  // inclusive scan over bins in decreasing key order (Hillis-Steele)
+  unsigned v = tid < (int)kKeyBins ? hist[kKeyBins - 1 - tid] : 0u;
+  for (unsigned off = 1; off < kKeyBins; off <<= 1) {
+    if (tid < (int)kKeyBins) scan[tid] = v;
+    __syncthreads();
+    if (tid < (int)kKeyBins && (unsigned)tid >= off) v += scan[tid - off];
+    __syncthreads();
+  }
+  if (tid < (int)kKeyBins) start[kKeyBins - 1 - tid] = v - hist[kKeyBins - 1 - tid];
+  __syncthreads();
+  for (unsigned t = tid; t < ntiles; t += NT) order[atomicAdd(&start[keys[t]], 1u)] = t;
 }
 
 template <int Q1, class FT, int TX, int TY, int H>
@@ -438,343 +478,392 @@ k_step(StepArgs A) {
   __shared__ double s_rd[4 * TS::NW];
   __shared__ unsigned s_list[NT];  // deferred nodes: local index | passes << 16
   __shared__ unsigned s_tail[2];   // list length, next entry to take
-
-  // Block -> tile: blocks are dealt to the 8 XCDs round-robin; renumber so
-  // that consecutive tiles (which share halo data) run on the same XCD.
-  const int nbx = gridDim.x, nblk = gridDim.x * gridDim.y;
-  int b = blockIdx.y * nbx + blockIdx.x;
-  if ((nblk & 7) == 0) b = (b & 7) * (nblk >> 3) + (b >> 3);
-  const int bx0 = (b % nbx) * TX, by0 = (b / nbx) * TY;
+  __shared__ unsigned s_tile;
+  __shared__ unsigned s_wmax[TS::NW];  // per wave: maximum passes of its nodes
 
   const int tid = threadIdx.x;
-  const int wave = tid >> 6, lane = tid & 63;
-  if (tid < 2) s_tail[tid] = 0u;  // ordered by the barriers below
-  const int X = bx0 + (wave % (TX / 8)) * 8 + (lane & 7);
-  const int Y = by0 + (wave / (TX / 8)) * 8 + (lane >> 3);
-  const bool active = (X < A.nx) && (Y < A.ny);
-  const size_t plane = (size_t)A.nx * A.ny;
-  const FT* __restrict__ fin = static_cast<const FT*>(A.f_in);
-  const double* __restrict__ gin = A.g_in;
+  const int ntx = (A.nx + TX - 1) / TX;
+  const unsigned ntiles = (unsigned)ntx * (unsigned)((A.ny + TY - 1) / TY);
+  if (tid < TS::NW) s_wmax[tid] = 0u;
 
-  // a1: seed gauge (eqs. 7-8) or the alternative seeds.
-  double ux = 0.0, uy = 0.0, T = L::TL;
-  size_t node = 0;
-  if (active) {
-    node = (size_t)Y * A.nx + X;
-    ux = gin[node];
-    uy = gin[plane + node];
-    T = gin[2 * plane + node];
-    if (A.seed_mode == 1) {
-      ux = 0.0;
-      uy = 0.0;
-      if (!A.isothermal) T = L::TL;
-    } else if (A.seed_mode == 2) {
-      ux = -ux;
-      uy = -uy;
+  // Persistent blocks: each block takes tiles from the queue until it is
+  // empty, so the cost spread between tiles (passes cluster along fronts) is
+  // balanced over all CUs without the hardware dispatcher.
+  for (;;) {
+    if (tid == 0) {
+      const unsigned g = atomicAdd(&A.queue->next, 1u);
+      s_tile = (A.tile_order && g < ntiles) ? A.tile_order[g] : g;
     }
-  }
+    if (tid < 2) s_tail[tid] = 0u;
+    __syncthreads();
+    const unsigned tile = s_tile;
+    if (tile >= ntiles) break;
+    const int ty = (int)(tile / (unsigned)ntx), tx = (int)tile - ty * ntx;
+    const int bx0 = tx * TX, by0 = ty * TY;
+    // thread index made opaque per tile, so that nothing derived from it is
+    // hoisted out of the tile loop and held in registers through the passes
+    int tl = tid;
+    asm volatile("" : "+v"(tl));
+    const int wave = tl >> 6, lane = tl & 63;
+    const int X = bx0 + (wave % (TX / 8)) * 8 + (lane & 7);
+    const int Y = by0 + (wave / (TX / 8)) * 8 + (lane >> 3);
+    const bool active = (X < A.nx) && (Y < A.ny);
+    const size_t plane = (size_t)A.nx * A.ny;
+    const FT* __restrict__ fin = static_cast<const FT*>(A.f_in);
+    const double* __restrict__ gin = A.g_in;
 
-  // ---- window placement and reference gauge from the seed gauges ----
-  int wx0, wy0;
-  double uxB, uyB, sB;
-  {
-    int v[4] = {INT_MAX, INT_MAX, INT_MAX, INT_MAX};
-    double a[4] = {0.0, 0.0, 0.0, 0.0};
-    const double s0 = sqrt(T * L::inv_TL);
-    const double sp = s0 * L::c(Q1 - 1);
-    if (active && isfinite(sp) && s0 > 0.0 && isfinite(ux) && isfinite(uy) &&
-        fabs(ux) < 1e9 && fabs(uy) < 1e9) {
-      v[0] = sat_floor(double(X) - ux - sp) - 2;
-      v[1] = -(sat_floor(double(X) - ux + sp) + 3);
-      v[2] = sat_floor(double(Y) - uy - sp) - 2;
-      v[3] = -(sat_floor(double(Y) - uy + sp) + 3);
-      a[0] = ux;
-      a[1] = uy;
-      a[2] = s0;
-      a[3] = 1.0;
-    }
-    block_reduce<TS::NW>(v, a, s_ri, s_rd);
-    if (a[3] > 0.0) {
-      uxB = a[0] / a[3];
-      uyB = a[1] / a[3];
-      sB = a[2] / a[3];
-    } else {  // no usable seed in the block: any reference gauge is exact
-      uxB = 0.0;
-      uyB = 0.0;
-      sB = 1.0;
-      v[0] = bx0 - H;
-      v[1] = -(bx0 + TX + H - 1);
-      v[2] = by0 - H;
-      v[3] = -(by0 + TY + H - 1);
-    }
-    const int xlo = v[0], xhi = -v[1], ylo = v[2], yhi = -v[3];
-    const int nxn = xhi - xlo + 1, nyn = yhi - ylo + 1;
-    wx0 = nxn <= WX ? xlo - (WX - nxn) / 2 : (int)(((long long)xlo + xhi) / 2) - WX / 2;
-    wy0 = nyn <= WY ? ylo - (WY - nyn) / 2 : (int)(((long long)ylo + yhi) / 2) - WY / 2;
-  }
-
-  // ---- stage the window in the reference gauge (eq. 4, G_{s->B}) ----
-  {
-    const double inv_sB = 1.0 / sB;
-    for (int k = tid; k < WN; k += NT) {
-      const int wy = k / WX, wx = k - wy * WX;
-      const int sx = wrap_index(wx0 + wx, A.nx, A.bc_x);
-      const int sy = wrap_index(wy0 + wy, A.ny, A.bc_y);
-      const size_t src = (size_t)sy * A.nx + sx;
-      double f[Q];
-#pragma unroll
-      for (int p = 0; p < Q; ++p) f[p] = double(fin[(size_t)p * plane + src]);
-      const double ss = sqrt(gin[2 * plane + src] * L::inv_TL);
-      const double r = ss * inv_sB;
-      double Gx[Q], Gy[Q];
-      transfer_factor<Q1, double>(r, (gin[src] - uxB) * inv_sB, Gx);
-      transfer_factor<Q1, double>(r, (gin[plane + src] - uyB) * inv_sB, Gy);
-      double Hm[Q];  // Hm[i][l] = sum_j Gy[l][j] f[i][j]
-#pragma unroll
-      for (int i = 0; i < Q1; ++i)
-#pragma unroll
-        for (int l = 0; l < Q1; ++l) {
-          double h = 0.0;
-#pragma unroll
-          for (int j = 0; j < Q1; ++j) h = fma(Gy[l * Q1 + j], f[i * Q1 + j], h);
-          Hm[i * Q1 + l] = h;
-        }
-#pragma unroll
-      for (int kk = 0; kk < Q1; ++kk)
-#pragma unroll
-        for (int l = 0; l < Q1; ++l) {
-          double t = 0.0;
-#pragma unroll
-          for (int i = 0; i < Q1; ++i) t = fma(Gx[kk * Q1 + i], Hm[i * Q1 + l], t);
-          s_f[(kk * Q1 + l) * WN + k] = FT(t);
-        }
-    }
-  }
-  __syncthreads();
-
-  const bool tail = A.fixed_iter == 0 && A.bulk_cap > 0 && A.bulk_cap < A.max_iter;
-  // step counters of this lane (its own node if finished in the bulk phase,
-  // plus the nodes it finishes as a tail-group leader)
-  unsigned long long c_nc = 0, c_nb = 0, c_sp = 0, c_mp = 0;
-  FT* __restrict__ fout = static_cast<FT*>(A.f_out);
-
-  unsigned passes = 0;
-  unsigned flags = 0;
-  bool deferred = false;
-  if (active) {
-    FT ft[Q];
-    double ux1 = ux, uy1 = uy, T1 = T, rho1 = 0.0;
-    bool bad = false;
-    for (;;) {
-      ++passes;
-      const double s = sqrt(T * L::inv_TL);
-      const double inv_s = 1.0 / s;
-      // a4 (window part): G_{B->n} rows are l_k(rB c + dB) per axis.
-      const double rB = sB * inv_s;
-      const double dBx = (uxB - ux) * inv_s, dBy = (uyB - uy) * inv_s;
-
-      // a2 + a3 (x axis) for every x speed: departure columns x0_i (as offsets
-      // o_i = x0_i - X), weights, and the rows of G_{B->n} along x.
-      int o[Q1];
-      double ax[Q1][4];
-      FT gbx[Q1][Q1];
-      int lo = INT_MAX, hi = INT_MIN;
-#pragma unroll
-      for (int i = 0; i < Q1; ++i) {
-        const double xd = double(X) - (s * L::c(i) + ux);
-        const double fl = floor(xd);
-        interp_weights(xd - (fl - 1.0), ax[i]);
-        o[i] = sat_floor(fl) - 1 - X;
-        double row[Q1];
-        transfer_row<Q1>(i, rB, dBx, row);
-#pragma unroll
-        for (int ip = 0; ip < Q1; ++ip) gbx[i][ip] = FT(row[ip]);
-        if (isfinite(xd)) {
-          lo = o[i] < lo ? o[i] : lo;
-          hi = o[i] + 3 > hi ? o[i] + 3 : hi;
-        }
+    // a1: seed gauge (eqs. 7-8) or the alternative seeds.
+    double ux = 0.0, uy = 0.0, T = L::TL;
+    size_t node = 0;
+    if (active) {
+      node = (size_t)Y * A.nx + X;
+      ux = gin[node];
+      uy = gin[plane + node];
+      T = gin[2 * plane + node];
+      if (A.seed_mode == 1) {
+        ux = 0.0;
+        uy = 0.0;
+        if (!A.isothermal) T = L::TL;
+      } else if (A.seed_mode == 2) {
+        ux = -ux;
+        uy = -uy;
       }
-      // The wave walks the union of its lanes' stencil columns once per y
-      // speed; every collocation point of a column is read from LDS once and
-      // its y contraction is shared by the four x speeds (each with its own
-      // weight, zero where the column is outside that speed's stencil).
-      lo = wave_min(lo);
-      hi = wave_max(hi);
-#pragma unroll 1
-      for (int j = 0; j < Q1; ++j) {
-        // a2 + a3 (y axis): the departure ordinate depends on c_j only.
-        const double yd = double(Y) - (s * speed_rt<Q1>(j) + uy);
-        const double fly = floor(yd);
-        double ay[4];
-        interp_weights(yd - (fly - 1.0), ay);
-        const int y0 = sat_floor(fly) - 1;
-        const LagRow Pj = lag_row<Q1>(j);
-        FT gby[Q1];
-        row_to<Q1, FT>(Pj, rB, dBy, gby);
-        FT acc_row[Q1];
-#pragma unroll
-        for (int i = 0; i < Q1; ++i) acc_row[i] = FT(0);
-#pragma unroll 1
-        for (int rel = lo; rel <= hi; ++rel) {
-          FT wx[Q1];
-          bool need = false;
-#pragma unroll
-          for (int i = 0; i < Q1; ++i) {
-            const int n = rel - o[i];
-            const bool in = (unsigned)n < 4u;
-            const double a = n == 0 ? ax[i][0] : n == 1 ? ax[i][1] : n == 2 ? ax[i][2] : ax[i][3];
-            wx[i] = in ? FT(a) : FT(0);
-            need = need || in;
-          }
-          if (!__any(need)) continue;
-#pragma unroll 2
-          for (int m = 0; m < 4; ++m) {
-            FT t[Q1];
-            column_values<Q1, FT, WX, WY, WN>(A, s_f, wx0, wy0, X + rel, y0 + m, need, gbx, gby,
-                                              Pj, ux, uy, inv_s, t);
-            const FT aym = FT(m == 0 ? ay[0] : m == 1 ? ay[1] : m == 2 ? ay[2] : ay[3]);
-#pragma unroll
-            for (int i = 0; i < Q1; ++i) acc_row[i] += (wx[i] * aym) * t[i];  // a5
-          }
-        }
-#pragma unroll
+    }
+
+    // ---- window placement and reference gauge from the seed gauges ----
+    int wx0, wy0;
+    double uxB, uyB, sB;
+    {
+      int v[4] = {INT_MAX, INT_MAX, INT_MAX, INT_MAX};
+      double a[4] = {0.0, 0.0, 0.0, 0.0};
+      const double s0 = sqrt(T * L::inv_TL);
+      const double sp = s0 * L::c(Q1 - 1);
+      if (active && isfinite(sp) && s0 > 0.0 && isfinite(ux) && isfinite(uy) &&
+          fabs(ux) < 1e9 && fabs(uy) < 1e9) {
+        v[0] = sat_floor(double(X) - ux - sp) - 2;
+        v[1] = -(sat_floor(double(X) - ux + sp) + 3);
+        v[2] = sat_floor(double(Y) - uy - sp) - 2;
+        v[3] = -(sat_floor(double(Y) - uy + sp) + 3);
+        a[0] = ux;
+        a[1] = uy;
+        a[2] = s0;
+        a[3] = 1.0;
+      }
+      block_reduce<TS::NW>(v, a, s_ri, s_rd);
+      if (a[3] > 0.0) {
+        uxB = a[0] / a[3];
+        uyB = a[1] / a[3];
+        sB = a[2] / a[3];
+      } else {  // no usable seed in the block: any reference gauge is exact
+        uxB = 0.0;
+        uyB = 0.0;
+        sB = 1.0;
+        v[0] = bx0 - H;
+        v[1] = -(bx0 + TX + H - 1);
+        v[2] = by0 - H;
+        v[3] = -(by0 + TY + H - 1);
+      }
+      const int xlo = v[0], xhi = -v[1], ylo = v[2], yhi = -v[3];
+      const int nxn = xhi - xlo + 1, nyn = yhi - ylo + 1;
+      wx0 = nxn <= WX ? xlo - (WX - nxn) / 2 : (int)(((long long)xlo + xhi) / 2) - WX / 2;
+      wy0 = nyn <= WY ? ylo - (WY - nyn) / 2 : (int)(((long long)ylo + yhi) / 2) - WY / 2;
+    }
+
+    // ---- stage the window in the reference gauge (eq. 4, G_{s->B}) ----
+    {
+      const double inv_sB = 1.0 / sB;
+      for (int k = tid; k < WN; k += NT) {
+        const int wy = k / WX, wx = k - wy * WX;
+        const int sx = wrap_index(wx0 + wx, A.nx, A.bc_x);
+        const int sy = wrap_index(wy0 + wy, A.ny, A.bc_y);
+        const size_t src = (size_t)sy * A.nx + sx;
+        double f[Q];
+  #pragma unroll
+        for (int p = 0; p < Q; ++p) f[p] = double(fin[(size_t)p * plane + src]);
+        const double ss = sqrt(gin[2 * plane + src] * L::inv_TL);
+        const double r = ss * inv_sB;
+        double Gx[Q], Gy[Q];
+        transfer_factor<Q1, double>(r, (gin[src] - uxB) * inv_sB, Gx);
+        transfer_factor<Q1, double>(r, (gin[plane + src] - uyB) * inv_sB, Gy);
+        double Hm[Q];  // Hm[i][l] = sum_j Gy[l][j] f[i][j]
+  #pragma unroll
         for (int i = 0; i < Q1; ++i)
-#pragma unroll
-          for (int jj = 0; jj < Q1; ++jj)
-            if (jj == j) ft[i * Q1 + jj] = acc_row[i];
-      }
-
-      // a6: moments in the peculiar frame of lambda_n (compensated sums).
-      FT r0 = 0, r0c = 0, mx = 0, mxc = 0, my = 0, myc = 0, e2 = 0, e2c = 0;
-#pragma unroll
-      for (int i = 0; i < Q1; ++i)
-#pragma unroll
-        for (int j = 0; j < Q1; ++j) {
-          const FT fv = ft[i * Q1 + j];
-          two_sum_acc(r0, r0c, fv);
-          two_sum_acc(mx, mxc, FT(L::c(i)) * fv);
-          two_sum_acc(my, myc, FT(L::c(j)) * fv);
-          two_sum_acc(e2, e2c, FT(L::c(i) * L::c(i) + L::c(j) * L::c(j)) * fv);
-        }
-      const int verdict = corrector<Q1>(A, s, ux, uy, T, double(r0) + double(r0c),
-                                        double(mx) + double(mxc), double(my) + double(myc),
-                                        double(e2) + double(e2c), passes, rho1, ux1, uy1, T1,
-                                        flags);
-      if (verdict == kBad) {
-        bad = true;
-        break;
-      }
-      if (verdict == kDone) break;
-      ux = ux1;
-      uy = uy1;
-      T = T1;
-      if (tail && (int)passes >= A.bulk_cap) {
-        deferred = true;  // continue in the tail with gauge (ux, uy, T)
-        break;
-      }
-    }
-
-    if (!deferred) {
-      if (bad) {
-        store_bad<Q1, FT>(A, fout, plane, node, 0, Q);
-        flags |= POND_ITERS_BAD;
-      } else {
-        // a8: f^{lambda_n} -> lambda_{n+1}, one full Kronecker transform.
-        const double s = sqrt(T * L::inv_TL), s1 = sqrt(T1 * L::inv_TL);
-        const double inv_s1 = 1.0 / s1, r = s * inv_s1;
-        double Rx[Q], Ry[Q];
-        transfer_factor<Q1, double>(r, (ux - ux1) * inv_s1, Rx);
-        transfer_factor<Q1, double>(r, (uy - uy1) * inv_s1, Ry);
-        FT Hm[Q];  // Hm[i][l] = sum_j Ry[l][j] ft[i][j]
-#pragma unroll
-        for (int i = 0; i < Q1; ++i)
-#pragma unroll
+  #pragma unroll
           for (int l = 0; l < Q1; ++l) {
-            FT h = FT(0);
-#pragma unroll
-            for (int j = 0; j < Q1; ++j) h += FT(Ry[l * Q1 + j]) * ft[i * Q1 + j];
+            double h = 0.0;
+  #pragma unroll
+            for (int j = 0; j < Q1; ++j) h = fma(Gy[l * Q1 + j], f[i * Q1 + j], h);
             Hm[i * Q1 + l] = h;
           }
-        // a9: BGK towards rho W (eq. 18), a10: store.
-        const FT omega = FT(1.0 / A.tau);
-#pragma unroll
-        for (int k = 0; k < Q1; ++k)
-#pragma unroll
+  #pragma unroll
+        for (int kk = 0; kk < Q1; ++kk)
+  #pragma unroll
           for (int l = 0; l < Q1; ++l) {
-            FT fr = FT(0);
-#pragma unroll
-            for (int i = 0; i < Q1; ++i) fr += FT(Rx[k * Q1 + i]) * Hm[i * Q1 + l];
-            const FT feq = FT(rho1 * (L::w(k) * L::w(l)));
-            fout[(size_t)(k * Q1 + l) * plane + node] = fr + omega * (feq - fr);
+            double t = 0.0;
+  #pragma unroll
+            for (int i = 0; i < Q1; ++i) t = fma(Gx[kk * Q1 + i], Hm[i * Q1 + l], t);
+            s_f[(kk * Q1 + l) * WN + k] = FT(t);
           }
-        A.g_out[node] = ux1;
-        A.g_out[plane + node] = uy1;
-        A.g_out[2 * plane + node] = T1;
       }
-      if (A.iters) A.iters[node] = (uint8_t)((passes & POND_ITERS_MASK) | flags);
-      c_nc = (flags & POND_ITERS_NONCONVERGED) ? 1 : 0;
-      c_nb = (flags & POND_ITERS_BAD) ? 1 : 0;
-      c_sp = passes;
-      c_mp = passes;
     }
-  }
-
-  // ---- block tail: unconverged nodes, 16 lanes each, all waves of the block ----
-  // A deferred node's next gauge goes through its output gauge slot (read
-  // back with L1-bypassing loads after the barrier); its local index and pass
-  // count go to an LDS list that the block's 16-lane groups drain.
-  if (tail) {
-    if (deferred) {
-      A.g_out[node] = ux;
-      A.g_out[plane + node] = uy;
-      A.g_out[2 * plane + node] = T;
-      const unsigned slot = atomicAdd(&s_tail[0], 1u);
-      s_list[slot] = (unsigned)tid | (passes << 16);
-    }
-    __threadfence_block();
     __syncthreads();
-    const unsigned count = s_tail[0];
-    if (count) {
+
+    const bool tail = A.fixed_iter == 0 && A.bulk_cap > 0 && A.bulk_cap < A.max_iter;
+    // step counters of this lane for the tile (its own node if finished in
+    // the bulk phase, plus the nodes it finishes as a tail-group leader)
+    unsigned long long c_nc = 0, c_nb = 0, c_sp = 0, c_mp = 0;
+    FT* __restrict__ fout = static_cast<FT*>(A.f_out);
+
+    unsigned passes = 0;
+    unsigned flags = 0;
+    bool deferred = false;
+    if (active) {
+      FT ft[Q];
+      double ux1 = ux, uy1 = uy, T1 = T, rho1 = 0.0;
+      bool bad = false;
       for (;;) {
-        unsigned e = 0;
-        if ((lane & 15) == 0) e = atomicAdd(&s_tail[1], 1u);
-        e = __shfl(e, lane & ~15);
-        const bool has = e < count;
-        if (__all(!has)) break;
-        const unsigned ent = has ? s_list[e] : 0u;
-        const int ltid = (int)(ent & 0xFFFF);
-        const int lw = ltid >> 6, ll = ltid & 63;
-        const int tX = bx0 + (lw % (TX / 8)) * 8 + (ll & 7);
-        const int tY = by0 + (lw / (TX / 8)) * 8 + (ll >> 3);
-        double tux = 0.0, tuy = 0.0, tT = L::TL;
-        if (has) {
-          const size_t tnode = (size_t)tY * A.nx + tX;
-          tux = __hip_atomic_load(&A.g_out[tnode], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          tuy = __hip_atomic_load(&A.g_out[plane + tnode], __ATOMIC_RELAXED,
-                                  __HIP_MEMORY_SCOPE_AGENT);
-          tT = __hip_atomic_load(&A.g_out[2 * plane + tnode], __ATOMIC_RELAXED,
-                                 __HIP_MEMORY_SCOPE_AGENT);
+        ++passes;
+        const double s = sqrt(T * L::inv_TL);
+        const double inv_s = 1.0 / s;
+        // a4 (window part): G_{B->n} rows are l_k(rB c + dB) per axis.
+        const double rB = sB * inv_s;
+        const double dBx = (uxB - ux) * inv_s, dBy = (uyB - uy) * inv_s;
+
+        // a2 + a3 (x axis) for every x speed: departure columns x0_i (as offsets
+        // o_i = x0_i - X), weights, and the rows of G_{B->n} along x.
+        int o[Q1];
+        double ax[Q1][4];
+        FT gbx[Q1][Q1];
+        int lo = INT_MAX, hi = INT_MIN;
+  #pragma unroll
+        for (int i = 0; i < Q1; ++i) {
+          const double xd = double(X) - (s * L::c(i) + ux);
+          const double fl = floor(xd);
+          interp_weights(xd - (fl - 1.0), ax[i]);
+          o[i] = sat_floor(fl) - 1 - X;
+          double row[Q1];
+          transfer_row<Q1>(i, rB, dBx, row);
+  #pragma unroll
+          for (int ip = 0; ip < Q1; ++ip) gbx[i][ip] = FT(row[ip]);
+          if (isfinite(xd)) {
+            lo = o[i] < lo ? o[i] : lo;
+            hi = o[i] + 3 > hi ? o[i] + 3 : hi;
+          }
         }
-        tail_group<Q1, FT, WX, WY, WN>(A, s_f, wx0, wy0, uxB, uyB, sB, has, tX, tY, tux, tuy, tT,
-                                       ent >> 16, c_nc, c_nb, c_sp, c_mp);
+        // The wave walks the union of its lanes' stencil columns once per y
+        // speed; every collocation point of a column is read from LDS once and
+        // its y contraction is shared by the four x speeds (each with its own
+        // weight, zero where the column is outside that speed's stencil).
+        lo = wave_min(lo);
+        hi = wave_max(hi);
+  #pragma unroll 1
+        for (int j = 0; j < Q1; ++j) {
+          // a2 + a3 (y axis): the departure ordinate depends on c_j only.
+          const double yd = double(Y) - (s * speed_rt<Q1>(j) + uy);
+          const double fly = floor(yd);
+          double ay[4];
+          interp_weights(yd - (fly - 1.0), ay);
+          const int y0 = sat_floor(fly) - 1;
+          const LagRow Pj = lag_row<Q1>(j);
+          FT gby[Q1];
+          row_to<Q1, FT>(Pj, rB, dBy, gby);
+          FT acc_row[Q1];
+  #pragma unroll
+          for (int i = 0; i < Q1; ++i) acc_row[i] = FT(0);
+  #pragma unroll 1
+          for (int rel = lo; rel <= hi; ++rel) {
+            FT wx[Q1];
+            bool need = false;
+  #pragma unroll
+            for (int i = 0; i < Q1; ++i) {
+              const int n = rel - o[i];
+              const bool in = (unsigned)n < 4u;
+              const double a = n == 0 ? ax[i][0] : n == 1 ? ax[i][1] : n == 2 ? ax[i][2] : ax[i][3];
+              wx[i] = in ? FT(a) : FT(0);
+              need = need || in;
+            }
+            if (!__any(need)) continue;
+  #pragma unroll 2
+            for (int m = 0; m < 4; ++m) {
+              FT t[Q1];
+              column_values<Q1, FT, WX, WY, WN>(A, s_f, wx0, wy0, X + rel, y0 + m, need, gbx, gby,
+                                                Pj, ux, uy, inv_s, t);
+              const FT aym = FT(m == 0 ? ay[0] : m == 1 ? ay[1] : m == 2 ? ay[2] : ay[3]);
+  #pragma unroll
+              for (int i = 0; i < Q1; ++i) acc_row[i] += (wx[i] * aym) * t[i];  // a5
+            }
+          }
+  #pragma unroll
+          for (int i = 0; i < Q1; ++i)
+  #pragma unroll
+            for (int jj = 0; jj < Q1; ++jj)
+              if (jj == j) ft[i * Q1 + jj] = acc_row[i];
+        }
+
+        // a6: moments in the peculiar frame of lambda_n (compensated sums).
+        FT r0 = 0, r0c = 0, mx = 0, mxc = 0, my = 0, myc = 0, e2 = 0, e2c = 0;
+  #pragma unroll
+        for (int i = 0; i < Q1; ++i)
+  #pragma unroll
+          for (int j = 0; j < Q1; ++j) {
+            const FT fv = ft[i * Q1 + j];
+            two_sum_acc(r0, r0c, fv);
+            two_sum_acc(mx, mxc, FT(L::c(i)) * fv);
+            two_sum_acc(my, myc, FT(L::c(j)) * fv);
+            two_sum_acc(e2, e2c, FT(L::c(i) * L::c(i) + L::c(j) * L::c(j)) * fv);
+          }
+        const int verdict = corrector<Q1>(A, s, ux, uy, T, double(r0) + double(r0c),
+                                          double(mx) + double(mxc), double(my) + double(myc),
+                                          double(e2) + double(e2c), passes, rho1, ux1, uy1, T1,
+                                          flags);
+        if (verdict == kBad) {
+          bad = true;
+          break;
+        }
+        if (verdict == kDone) break;
+        ux = ux1;
+        uy = uy1;
+        T = T1;
+        if (tail && (int)passes >= A.bulk_cap) {
+          deferred = true;  // continue in the tail with gauge (ux, uy, T)
+          break;
+        }
+      }
+
+      if (!deferred) {
+        if (bad) {
+          store_bad<Q1, FT>(A, fout, plane, node, 0, Q);
+          flags |= POND_ITERS_BAD;
+        } else {
+          // a8: f^{lambda_n} -> lambda_{n+1}, one full Kronecker transform.
+          const double s = sqrt(T * L::inv_TL), s1 = sqrt(T1 * L::inv_TL);
+          const double inv_s1 = 1.0 / s1, r = s * inv_s1;
+          double Rx[Q], Ry[Q];
+          transfer_factor<Q1, double>(r, (ux - ux1) * inv_s1, Rx);
+          transfer_factor<Q1, double>(r, (uy - uy1) * inv_s1, Ry);
+          FT Hm[Q];  // Hm[i][l] = sum_j Ry[l][j] ft[i][j]
+  #pragma unroll
+          for (int i = 0; i < Q1; ++i)
+  #pragma unroll
+            for (int l = 0; l < Q1; ++l) {
+              FT h = FT(0);
+  #pragma unroll
+              for (int j = 0; j < Q1; ++j) h += FT(Ry[l * Q1 + j]) * ft[i * Q1 + j];
+              Hm[i * Q1 + l] = h;
+            }
+          // a9: BGK towards rho W (eq. 18), a10: store.
+          const FT omega = FT(1.0 / A.tau);
+  #pragma unroll
+          for (int k = 0; k < Q1; ++k)
+  #pragma unroll
+            for (int l = 0; l < Q1; ++l) {
+              FT fr = FT(0);
+  #pragma unroll
+              for (int i = 0; i < Q1; ++i) fr += FT(Rx[k * Q1 + i]) * Hm[i * Q1 + l];
+              const FT feq = FT(rho1 * (L::w(k) * L::w(l)));
+              fout[(size_t)(k * Q1 + l) * plane + node] = fr + omega * (feq - fr);
+            }
+          A.g_out[node] = ux1;
+          A.g_out[plane + node] = uy1;
+          A.g_out[2 * plane + node] = T1;
+        }
+        if (A.iters) A.iters[node] = (uint8_t)((passes & POND_ITERS_MASK) | flags);
+        c_nc += (flags & POND_ITERS_NONCONVERGED) ? 1 : 0;
+        c_nb += (flags & POND_ITERS_BAD) ? 1 : 0;
+        c_sp += passes;
+        c_mp = passes > c_mp ? passes : c_mp;
       }
     }
-  }
 
-  if (A.counters) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-      c_nc += __shfl_xor(c_nc, off);
-      c_nb += __shfl_xor(c_nb, off);
-      c_sp += __shfl_xor(c_sp, off);
-      const unsigned long long o = __shfl_xor(c_mp, off);
-      c_mp = o > c_mp ? o : c_mp;
+    {  // cost key of the tile: per wave, the most passes of its nodes so far
+      const int wm = wave_max((int)passes);
+      if (lane == 0) s_wmax[wave] = (unsigned)wm;
     }
-    if (lane == 0) {
-      if (c_nc) atomicAdd(&A.counters->nonconverged, c_nc);
-      if (c_nb) atomicAdd(&A.counters->bad, c_nb);
-      atomicAdd(&A.counters->sum_passes, c_sp);
-      atomicMax(&A.counters->max_passes, c_mp);
+
+    // ---- block tail: unconverged nodes, 16 lanes each, all waves of the block ----
+    // A deferred node's next gauge goes through its output gauge slot (read
+    // back with L1-bypassing loads after the barrier); its local index and pass
+    // count go to an LDS list that the block's 16-lane groups drain.
+    if (tail) {
+      if (deferred) {
+        A.g_out[node] = ux;
+        A.g_out[plane + node] = uy;
+        A.g_out[2 * plane + node] = T;
+        const unsigned slot = atomicAdd(&s_tail[0], 1u);
+        s_list[slot] = (unsigned)tid | (passes << 16);
+      }
+      __threadfence_block();
+      __syncthreads();
+      const unsigned count = s_tail[0];
+      if (count) {
+        for (;;) {
+          unsigned e = 0;
+          if ((lane & 15) == 0) e = atomicAdd(&s_tail[1], 1u);
+          e = __shfl(e, lane & ~15);
+          const bool has = e < count;
+          if (__all(!has)) break;
+          const unsigned ent = has ? s_list[e] : 0u;
+          const int ltid = (int)(ent & 0xFFFF);
+          const int lw = ltid >> 6, ll = ltid & 63;
+          const int tX = bx0 + (lw % (TX / 8)) * 8 + (ll & 7);
+          const int tY = by0 + (lw / (TX / 8)) * 8 + (ll >> 3);
+          double tux = 0.0, tuy = 0.0, tT = L::TL;
+          if (has) {
+            const size_t tnode = (size_t)tY * A.nx + tX;
+            tux = __hip_atomic_load(&A.g_out[tnode], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            tuy = __hip_atomic_load(&A.g_out[plane + tnode], __ATOMIC_RELAXED,
+                                    __HIP_MEMORY_SCOPE_AGENT);
+            tT = __hip_atomic_load(&A.g_out[2 * plane + tnode], __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+          }
+          tail_group<Q1, FT, WX, WY, WN>(A, s_f, wx0, wy0, uxB, uyB, sB, has, tX, tY, tux, tuy, tT,
+                                         ent >> 16, &s_wmax[lw], c_nc, c_nb, c_sp, c_mp);
+        }
+      }
+    }
+    if (A.counters) {
+  #pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        c_nc += __shfl_xor(c_nc, off);
+        c_nb += __shfl_xor(c_nb, off);
+        c_sp += __shfl_xor(c_sp, off);
+        const unsigned long long o = __shfl_xor(c_mp, off);
+        c_mp = o > c_mp ? o : c_mp;
+      }
+      if (lane == 0) {
+        if (c_nc) atomicAdd(&A.counters->nonconverged, c_nc);
+        if (c_nb) atomicAdd(&A.counters->bad, c_nb);
+        atomicAdd(&A.counters->sum_passes, c_sp);
+        atomicMax(&A.counters->max_passes, c_mp);
+      }
+    }
+    __syncthreads();  // LDS of this tile is free
+    if (tid == 0) {
+      unsigned key = 0;
+#pragma unroll
+      for (int w = 0; w < TS::NW; ++w) {
+        key += s_wmax[w];
+        s_wmax[w] = 0u;
+      }
+      if (A.tile_keys) A.tile_keys[tile] = (uint16_t)(key < kKeyBins ? key : kKeyBins - 1);
+    }
+  }  // tile loop
+
+  // The last block out orders the tiles for the next launch by this step's
+  // keys and resets the queue.  Every block has taken its last tile before it
+  // counts itself out, so the order array is no longer read.
+  if (tid == 0) {
+    __threadfence();
+    s_tile = atomicAdd(&A.queue->done, 1u) == gridDim.x - 1 ? 1u : 0u;
+  }
+  __syncthreads();
+  if (s_tile) {
+    __threadfence();
+    if (A.tile_keys && A.tile_order_next)
+      order_tiles<NT>(A.tile_keys, A.tile_order_next, ntiles, reinterpret_cast<unsigned*>(s_f));
+    if (tid == 0) {
+      atomicExch(&A.queue->next, 0u);
+      atomicExch(&A.queue->done, 0u);
     }
   }
 }
@@ -796,16 +885,42 @@ struct StepTile {
   static constexpr int TX = POND_TILE_X, TY = POND_TILE_Y, H = Q1 == 4 ? POND_HALO : 4;
 };
 
+// Persistent grid: as many blocks as the device holds at once (CUs x blocks
+// per CU), never more than there are tiles.
 template <int Q1, class FT>
 hipError_t launch_step_t(const StepArgs& a, hipStream_t s) {
   using ST = StepTile<Q1, FT>;
-  dim3 block(ST::TX * ST::TY);
-  dim3 grid((a.nx + ST::TX - 1) / ST::TX, (a.ny + ST::TY - 1) / ST::TY);
-  hipLaunchKernelGGL((k_step<Q1, FT, ST::TX, ST::TY, ST::H>), grid, block, 0, s, a);
+  constexpr int kMaxDev = 64;
+  static int resident[kMaxDev] = {0};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDev) return hipErrorInvalidDevice;
+  if (resident[dev] == 0) {
+    int cus = 0, per_cu = 0;
+    e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &per_cu, reinterpret_cast<const void*>(&k_step<Q1, FT, ST::TX, ST::TY, ST::H>),
+        ST::TX * ST::TY, 0);
+    if (e != hipSuccess) return e;
+    resident[dev] = (cus > 0 ? cus : 1) * (per_cu > 0 ? per_cu : 1);
+  }
+  const long long tiles =
+      (long long)((a.nx + ST::TX - 1) / ST::TX) * ((a.ny + ST::TY - 1) / ST::TY);
+  const int nblk = (int)(tiles < resident[dev] ? tiles : resident[dev]);
+  hipLaunchKernelGGL((k_step<Q1, FT, ST::TX, ST::TY, ST::H>), dim3(nblk), dim3(ST::TX * ST::TY), 0,
+                     s, a);
   return hipGetLastError();
 }
 
 }  // namespace
+
+unsigned step_tile_count(const pond_config& c) {
+  // every variant uses the same tile shape
+  using ST = StepTile<4, double>;
+  return (unsigned)(((c.nx + ST::TX - 1) / ST::TX) * (long long)((c.ny + ST::TY - 1) / ST::TY));
+}
 
 hipError_t launch_step(const pond_config& c, const StepArgs& a, hipStream_t s) {
   const bool f64 = c.precision == POND_F64;
