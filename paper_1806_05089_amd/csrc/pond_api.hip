@@ -77,7 +77,8 @@ int ensure_tile_arrays(Slot* sl, size_t ntiles, hipStream_t s) {
   }
   sl->order_nx = sl->order_ny = -1;
   e = hipMalloc(reinterpret_cast<void**>(&sl->keys), ntiles * sizeof(uint16_t));
-  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&sl->order), ntiles * sizeof(unsigned));
+  if (e == hipSuccess)
+    e = hipMalloc(reinterpret_cast<void**>(&sl->order), ntiles * sizeof(unsigned));
   if (e != hipSuccess) {
     (void)hipFree(sl->keys);
     sl->keys = nullptr;
@@ -284,9 +285,12 @@ int pond_step_adjoint(const pond_config* cfg, const pond_state* in, const pond_s
       overlap(adj_in->f, afb, in->f, fb) || overlap(adj_in->g, agb, in->g, agb) ||
       overlap(adj_in->f, afb, adj_in->g, agb))
     return fail(POND_E_ALIAS, "pond_step_adjoint: adj_in overlaps another buffer");
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  Slot* slot = nullptr;
+  if ((rc = slot_for_stream(s, &slot))) return rc;
   hipError_t e = pond::launch_adjoint(*cfg, in->f, in->g, out_fwd->iters, (const double*)adj_out->f,
                                       adj_out->g, (double*)adj_in->f, adj_in->g, adj_tau,
-                                      static_cast<hipStream_t>(hip_stream));
+                                      &slot->dev->queue, s);
   if (e == hipErrorNotSupported) return fail(POND_E_UNSUPPORTED, "pond_step_adjoint: not available");
   if (e != hipSuccess) return hip_fail(e, "pond_step_adjoint launch");
   return POND_OK;

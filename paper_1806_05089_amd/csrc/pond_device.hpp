@@ -178,6 +178,36 @@ __device__ __forceinline__ void interp_weights(double t, double* a) {
   a[3] = t0 * t1 * t2 * (1.0 / 6.0);
 }
 
+// Wave-wide maximum of a non-negative int.  In a branch that only part of
+// the wave executes, a cross-lane read (ds_bpermute) from an inactive lane
+// returns 0, which is neutral for this maximum.
+__device__ __forceinline__ int wave_max_nonneg(int v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const int o = __shfl_xor(v, off);
+    v = o > v ? o : v;
+  }
+  return v;
+}
+
+// Wave-wide range [wlo, whi] of the stencil columns of the active lanes that
+// have one (has = false: the lane adds nothing).  Both bounds are reduced as
+// maxima of positive codes, so inactive lanes add nothing either.  Column
+// offsets come from saturated floors (|x| <= 1e9), so the codes stay below
+// 2^31.  Returns false if no active lane has a range.
+__device__ __forceinline__ bool wave_column_range(int lo, int hi, bool has, int& wlo, int& whi) {
+  constexpr int kBias = 1 << 30;
+  const int a = wave_max_nonneg(has ? kBias - lo : 0);
+  const int b = wave_max_nonneg(has ? hi + kBias : 0);
+  wlo = kBias - a;
+  whi = b - kBias;
+  return a > 0;
+}
+
+// A wave walks the union of its lanes' stencil columns; a lane whose stencil
+// lies further than this from its node is handled on its own instead.
+constexpr int kFarColumns = 256;
+
 // Stencil index -> node index: periodic wrap or zero-gradient clamp.
 __device__ __forceinline__ int wrap_index(int i, int n, int bc) {
   if (bc == 0) {

@@ -65,6 +65,7 @@ hipError_t launch_moments(const pond_config& c, const void* f, const double* g, 
 hipError_t launch_zero_u64(unsigned long long* p, int n, hipStream_t s);
 hipError_t launch_adjoint(const pond_config& c, const void* f_in, const double* g_in,
                           const uint8_t* iters, const double* adj_f_out, const double* adj_g_out,
-                          double* adj_f_in, double* adj_g_in, double* adj_tau, hipStream_t s);
+                          double* adj_f_in, double* adj_g_in, double* adj_tau, TileQueue* queue,
+                          hipStream_t s);
 
 }  // namespace pond

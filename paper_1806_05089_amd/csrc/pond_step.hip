@@ -169,24 +169,6 @@ __device__ __forceinline__ FT pair_value(const StepArgs& A, const FT* s_f, int w
   return t;
 }
 
-// Wave-wide minimum / maximum of an int.
-__device__ __forceinline__ int wave_min(int v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    const int o = __shfl_xor(v, off);
-    v = o < v ? o : v;
-  }
-  return v;
-}
-__device__ __forceinline__ int wave_max(int v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    const int o = __shfl_xor(v, off);
-    v = o > v ? o : v;
-  }
-  return v;
-}
-
 // a4 for one collocation point (gx, gy) and every x speed i:
 // t[i] = [G_{lambda_s -> lambda_n} f_s]_(i,j).  On the LDS window the y
 // contraction with the G_{B->n} row gby is done once and shared; outside it
@@ -608,7 +590,9 @@ k_step(StepArgs A) {
     }
     __syncthreads();
 
-    const bool tail = A.fixed_iter == 0 && A.bulk_cap > 0 && A.bulk_cap < A.max_iter;
+    // adaptive runs move nodes still unconverged after bulk_cap passes to the
+    // block tail
+    const bool capped = A.fixed_iter == 0 && A.bulk_cap > 0 && A.bulk_cap < A.max_iter;
     // step counters of this lane for the tile (its own node if finished in
     // the bulk phase, plus the nodes it finishes as a tail-group leader)
     unsigned long long c_nc = 0, c_nb = 0, c_sp = 0, c_mp = 0;
@@ -635,6 +619,7 @@ k_step(StepArgs A) {
         double ax[Q1][4];
         FT gbx[Q1][Q1];
         int lo = INT_MAX, hi = INT_MIN;
+        bool has = false, far = false;
   #pragma unroll
         for (int i = 0; i < Q1; ++i) {
           const double xd = double(X) - (s * L::c(i) + ux);
@@ -648,14 +633,23 @@ k_step(StepArgs A) {
           if (isfinite(xd)) {
             lo = o[i] < lo ? o[i] : lo;
             hi = o[i] + 3 > hi ? o[i] + 3 : hi;
+            has = true;
+            far = far || o[i] < -kFarColumns || o[i] > kFarColumns;
           }
+        }
+        // A departure point further than kFarColumns nodes away (|v| dt of
+        // hundreds of nodes) would stretch the wave's column walk: such a node
+        // finishes in the block tail, which walks its own stencils.
+        if (far) {
+          --passes;
+          deferred = true;
+          break;
         }
         // The wave walks the union of its lanes' stencil columns once per y
         // speed; every collocation point of a column is read from LDS once and
         // its y contraction is shared by the four x speeds (each with its own
         // weight, zero where the column is outside that speed's stencil).
-        lo = wave_min(lo);
-        hi = wave_max(hi);
+        if (!wave_column_range(lo, hi, has, lo, hi)) hi = lo - 1;
   #pragma unroll 1
         for (int j = 0; j < Q1; ++j) {
           // a2 + a3 (y axis): the departure ordinate depends on c_j only.
@@ -724,7 +718,7 @@ k_step(StepArgs A) {
         ux = ux1;
         uy = uy1;
         T = T1;
-        if (tail && (int)passes >= A.bulk_cap) {
+        if (capped && (int)passes >= A.bulk_cap) {
           deferred = true;  // continue in the tail with gauge (ux, uy, T)
           break;
         }
@@ -776,7 +770,7 @@ k_step(StepArgs A) {
     }
 
     {  // cost key of the tile: per wave, the most passes of its nodes so far
-      const int wm = wave_max((int)passes);
+      const int wm = wave_max_nonneg((int)passes);
       if (lane == 0) s_wmax[wave] = (unsigned)wm;
     }
 
@@ -784,7 +778,7 @@ k_step(StepArgs A) {
     // A deferred node's next gauge goes through its output gauge slot (read
     // back with L1-bypassing loads after the barrier); its local index and pass
     // count go to an LDS list that the block's 16-lane groups drain.
-    if (tail) {
+    {
       if (deferred) {
         A.g_out[node] = ux;
         A.g_out[plane + node] = uy;

@@ -133,6 +133,11 @@ def uniform(nx: int, ny: int, rho: float = 1.0, ux: float = 0.0, uy: float = 0.0
                     np.full((ny, nx), T), tau, isothermal, 0, 0, 1, {})
 
 
+def shifted(w: Workload, dux: float, duy: float = 0.0) -> Workload:
+    """The same fields riding on an extra uniform velocity (dux, duy)."""
+    return dataclasses.replace(w, name=w.name + "_shifted", ux=w.ux + dux, uy=w.uy + duy)
+
+
 def random_smooth(nx: int, ny: int, seed: int = 0, mach: float = 0.3, T0: float = 1.0,
                   dT: float = 0.2, drho: float = 0.1, modes: int = 3, tau: float = 0.6) -> Workload:
     """Smooth random periodic fields (a few Fourier modes per field) for parity tests."""

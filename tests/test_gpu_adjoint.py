@@ -61,6 +61,10 @@ CASES = [
     ("seed_mode_2", lambda: workloads.random_smooth(16, 16, seed=2, mach=0.2), 4, {"seed_mode": 2}),
     ("d2q9", lambda: workloads.random_smooth(18, 16, seed=3, mach=0.2, T0=1.0), 3, {}),
     ("mach5", lambda: workloads.mach5(16, seed=0), 4, {}),
+    # departure points 300 nodes upstream: lanes walk their own stencils
+    ("far_stencils_u300", lambda: workloads.shifted(workloads.random_smooth(16, 16, seed=6,
+                                                                           mach=0.2), 300.0),
+     4, {}),
 ]
 
 

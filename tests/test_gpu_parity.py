@@ -58,6 +58,10 @@ CASES_FIXED = [
     ("mach5_24x20", lambda: workloads.mach5(24, seed=0), 4, 2),
     ("ragged_67x5", lambda: workloads.random_smooth(67, 5, seed=2, mach=0.6), 4, 3),
     ("d2q9_smooth_40x36", lambda: workloads.random_smooth(40, 36, seed=3, T0=1.0 / 3.0, mach=0.2), 3, 3),
+    # T = 50: each node's stencils span ~37 columns, more than a wave walks
+    # jointly, and reach past the LDS window (HBM collocation points)
+    ("hot_gas_48x40", lambda: workloads.random_smooth(48, 40, seed=12, T0=50.0, dT=0.1, mach=0.3),
+     4, 2),
 ]
 
 
@@ -233,6 +237,50 @@ def test_full_size_sampled_riemann_1024(gpu):
         gg = out.g.cpu().numpy().reshape(3, -1)[:, pts]
         errs = state_errors(fg, gg, fo, go, u_scale=1.0, T_scale=float(np.max(w.T)))
         assert max(errs.values()) < tol, (prec, errs)
+
+
+def _far_base(q):
+    return workloads.random_smooth(48, 40, seed=13, mach=0.3, T0=1.0 if q == 4 else 1.0 / 3.0)
+
+
+@pytest.mark.parametrize("q", [4, 3])
+def test_far_stencils_fixed_passes(gpu, q):
+    """Departure points 300 nodes upstream: such nodes leave the wave's joint
+    column walk and finish in the block tail.  Checked against the oracle at
+    the same velocities; the oracle's lab-frame moments (eqs. 10-12 as
+    printed) cancel terms of size |u|^2, so its own rounding is ~|u|^2 eps."""
+    U = 300.0
+    w = workloads.shifted(_far_base(q), U)
+    cfg = _cfg(w, q=q, fixed_iter=2)
+    (fg, gg, ig), (fo, go, io, _) = _run_both(w, cfg)
+    tol = 10.0 * U * U * np.finfo(np.float64).eps
+    errs = state_errors(fg, gg, fo, go, u_scale=U, T_scale=float(np.max(w.T)))
+    assert max(errs.values()) < tol, (tol, errs)
+    assert np.all((ig & pond.POND_ITERS_MASK) == 2)
+
+
+def test_far_stencils_adaptive_galilean(gpu):
+    """Converged steps are Galilean invariant under integer shifts, so the
+    adaptive run at u + 300 equals the oracle's run at u rolled by 300 nodes
+    per step, with 300 added to u_x (to the App. E tolerance).  A truncated
+    iteration is not: its seed is the node's own stored gauge, which the
+    shift does not move."""
+    base = _far_base(4)
+    w = workloads.shifted(base, 300.0)
+    cfg = _cfg(w, max_iter=20)
+    st = pond.init(cfg, w.rho, w.ux, w.uy, w.T)
+    out, _ = pond.step(cfg, st, nsteps=2)
+    f0, g0 = oracle.init(base.rho, base.ux, base.uy, base.T, q=4)
+    oc = _ocfg(_cfg(base, max_iter=20))
+    for _ in range(2):
+        f0, g0, io, _ = oracle.step(f0, g0, oc)
+    shift = (300 * 2) % 48
+    fo, go = np.roll(f0, shift, axis=-1), np.roll(g0, shift, axis=-1)
+    go[0] += 300.0
+    # (pass counts differ with the seeds; the converged values do not)
+    errs = state_errors(out.f.double().cpu().numpy(), out.g.cpu().numpy(), fo, go,
+                        u_scale=300.0, T_scale=float(np.max(w.T)))
+    assert max(errs.values()) < 1e-9, errs
 
 
 def test_tile_order_multi_step_ragged(gpu):

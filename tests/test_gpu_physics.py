@@ -92,7 +92,7 @@ def test_sod_fp32_vs_fp64_error():
     assert e["rho"] < 5e-3 and e["ux"] < 5e-3 and e["T"] < 5e-3
 
 
-@pytest.mark.parametrize("U,T", [(0.0, 1.0), (5.0, 1.0), (30.0, 0.5), (100.0, 2.0)])
+@pytest.mark.parametrize("U,T", [(0.0, 1.0), (5.0, 1.0), (30.0, 0.5), (100.0, 2.0), (300.0, 1.0)])
 def test_uniform_flow_any_mach(U, T):
     w = workloads.uniform(64, 48, rho=1.3, ux=U, uy=-0.3 * U, T=T)
     cfg = _cfg(w)
