@@ -23,6 +23,21 @@ Workloads (all synthetic; the paper uses no dataset):
   an i.i.d. Gaussian velocity perturbation 0.01 u0 N(0, 1).
 * ``riemann2d``: four-quadrant 2-D Riemann problem; per quadrant rho ~
   U[0.5, 1.5], p ~ U[0.3, 1.5], T = p / rho, u_x, u_y ~ U[-0.8, 0.8] sqrt(T).
+
+D2Q9 experiments of the paper (lattice temperature T_L = 1/3):
+
+* ``shear_wave``: isothermal plane shear wave whose wave vector is tilted by
+  pi/4: transverse velocity A sin(2 pi (x + y) / N) along (-1, 1)/sqrt2,
+  advection Ma_a sqrt(T) along the wave vector (1, 1)/sqrt2, on an N x N
+  periodic grid (wavelength N / sqrt2 along the diagonal).
+* ``sound_pulse``: gas at rest or advected (u = Ma_a sqrt(T)) with a Gaussian
+  pressure disturbance of amplitude 1e-3 at uniform density, 1-D periodic.
+* ``thermal_wave``: rho = rho0 + A sin(2 pi x / L) at uniform pressure
+  p = rho0 T0, advected with u = Ma_a sqrt(2 T0), 1-D periodic.
+* ``vortex``: isothermal vortex u_phi(r) = Ma_v c r exp((1 - r^2) / 2),
+  r = r'/R, c = sqrt(2 T), with the density that balances the centrifugal
+  force at uniform T, rho = exp(-Ma_v^2 exp(1 - r^2)), advected with
+  U = Ma_a c along x, periodic.
 """
 from __future__ import annotations
 
@@ -158,3 +173,58 @@ def random_smooth(nx: int, ny: int, seed: int = 0, mach: float = 0.3, T0: float 
     ux = mach * math.sqrt(T0) * field()
     uy = mach * math.sqrt(T0) * field()
     return Workload("random_smooth", rho, ux, uy, T, tau, 0, 0, 0, 1, {"seed": seed})
+
+
+TL_D2Q9 = 1.0 / 3.0
+
+
+def shear_wave(N: int = 128, T: float = TL_D2Q9, mach_a: float = 0.0, nu: float = 0.02,
+               A: float = 0.05) -> Workload:
+    """Tilted shear wave; tau from nu = T (tau - 1/2)."""
+    X, Y = _grid(N, N)
+    ut = A * np.sin(2 * math.pi * (X + Y) / N)   # transverse, along (-1, 1)/sqrt2
+    ul = mach_a * math.sqrt(T)                   # advection along (1, 1)/sqrt2
+    r2 = 1.0 / math.sqrt(2.0)
+    ux = r2 * (ul - ut)
+    uy = r2 * (ul + ut)
+    tau = 0.5 + nu / T
+    return Workload("shear_wave", np.ones((N, N)), ux, uy, np.full((N, N), T), tau, 1, 0, 0, 0,
+                    {"A": A, "k": 2 * math.pi * math.sqrt(2.0) / N, "nu": nu, "mach_a": mach_a})
+
+
+def sound_pulse(nx: int = 512, T0: float = TL_D2Q9, mach_a: float = 0.0, amp: float = 1e-3,
+                width: float = 4.0, tau: float = 0.6) -> Workload:
+    """Pressure disturbance carried by the temperature at uniform density."""
+    x = np.arange(nx, dtype=np.float64)
+    x0 = nx / 2.0
+    T = T0 * (1.0 + amp * np.exp(-((x - x0) / width) ** 2))
+    U = mach_a * math.sqrt(T0)
+    return Workload("sound_pulse", np.ones((1, nx)), np.full((1, nx), U), np.zeros((1, nx)),
+                    T[None], tau, 0, 0, 0, 0, {"x0": x0, "U": U, "T0": T0})
+
+
+def thermal_wave(L: int = 300, T0: float = TL_D2Q9, mach_a: float = 0.0, A: float = 1e-3,
+                 rho0: float = 1.0, tau: float = 0.6) -> Workload:
+    """Density wave at uniform pressure (an entropy wave); Ma_a = u / sqrt(2 T0)."""
+    x = np.arange(L, dtype=np.float64)
+    rho = rho0 + A * np.sin(2 * math.pi * x / L)
+    T = rho0 * T0 / rho
+    U = mach_a * math.sqrt(2.0 * T0)
+    return Workload("thermal_wave", rho[None], np.full((1, L), U), np.zeros((1, L)), T[None], tau,
+                    0, 0, 0, 0, {"k": 2 * math.pi / L, "U": U, "T0": T0, "A": A})
+
+
+def vortex(N: int = 128, R: float = 10.0, mach_v: float = 0.8, mach_a: float = 0.0,
+           T: float = TL_D2Q9, tau: float = 0.6) -> Workload:
+    """Vortex of radius R at the grid centre; Ma_v and Ma_a relative to sqrt(2 T)."""
+    X, Y = _grid(N, N)
+    c = math.sqrt(2.0 * T)
+    dx = (X - N / 2.0) / R
+    dy = (Y - N / 2.0) / R
+    r2 = dx * dx + dy * dy
+    amp = mach_v * c * np.exp((1.0 - r2) / 2.0)   # u_phi / r
+    ux = -amp * dy + mach_a * c
+    uy = amp * dx
+    rho = np.exp(-mach_v * mach_v * np.exp(1.0 - r2))
+    return Workload("vortex", rho, ux, uy, np.full((N, N), T), tau, 0, 0, 0, 0,
+                    {"R": R, "mach_v": mach_v, "mach_a": mach_a, "U": mach_a * c})
