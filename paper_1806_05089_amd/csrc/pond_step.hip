@@ -25,6 +25,18 @@
 #include "pond_device.hpp"
 #include "pond_internal.hpp"
 
+// Width of a wave's node tile (64 / width rows).  FP64: 8 x 8 (square tiles
+// cut the number of waves a front of slow-converging nodes crosses).  FP32:
+// 32 x 2, whose LDS reads of a collocation point are free of bank conflicts
+// (8 x 8 tiles spend half the LDS cycles in conflicts, which only the FP32
+// kernel feels).
+#ifndef POND_WAVE_TX_F64
+#define POND_WAVE_TX_F64 8
+#endif
+#ifndef POND_WAVE_TX_F32
+#define POND_WAVE_TX_F32 32
+#endif
+
 namespace pond {
 namespace {
 
@@ -36,7 +48,9 @@ struct TileShape {
   static constexpr int NT = TX * TY;
   static constexpr int NW = NT / 64;
   static constexpr size_t lds_bytes = (size_t)Q1 * Q1 * WN * sizeof(FT);
-  static_assert(TX % 8 == 0 && TY % 8 == 0, "waves are 8 x 8 node tiles");
+  static constexpr int WTX = sizeof(FT) == 8 ? POND_WAVE_TX_F64 : POND_WAVE_TX_F32;
+  static constexpr int WTY = 64 / WTX;  // wave tile
+  static_assert(TX % WTX == 0 && TY % WTY == 0, "waves tile the block");
   static_assert(lds_bytes + 1024 <= 160 * 1024, "window exceeds the 160 KiB LDS of a CU");
 };
 
@@ -169,18 +183,19 @@ __device__ __forceinline__ FT pair_value(const StepArgs& A, const FT* s_f, int w
   return t;
 }
 
-// a4 for one collocation point (gx, gy) and every x speed i:
-// t[i] = [G_{lambda_s -> lambda_n} f_s]_(i,j).  On the LDS window the y
-// contraction with the G_{B->n} row gby is done once and shared; outside it
-// the point is read from HBM and transformed directly (rows of G_{s->n}).
+// a4 + a5 for one collocation point (gx, gy) of a column, y weight aym:
+// on the LDS window the y contraction with the G_{B->n} row gby is weighted
+// and summed over the column's rows into hc (the x rows of G_{B->n} are
+// applied once per column by the caller, they do not depend on the row);
+// outside it the point is read from HBM, transformed directly with the rows
+// of G_{s->n} (which depend on the point's own gauge) and added to acc with
+// the x weights wx.
 template <int Q1, class FT, int WX, int WY, int WN>
-__device__ __forceinline__ void column_values(const StepArgs& A, const FT* s_f, int wx0, int wy0,
-                                              int gx, int gy, bool need, const FT (&gbx)[Q1][Q1],
-                                              const FT* gby, const LagRow& Pj, double ux,
-                                              double uy, double inv_s, FT* t) {
+__device__ __forceinline__ void column_point(const StepArgs& A, const FT* s_f, int wx0, int wy0,
+                                             int gx, int gy, bool need, FT aym, const FT* wx,
+                                             const FT* gby, const LagRow& Pj, double ux,
+                                             double uy, double inv_s, FT* hc, FT* acc) {
   using L = Lat<Q1>;
-#pragma unroll
-  for (int i = 0; i < Q1; ++i) t[i] = FT(0);
   const int lx = gx - wx0, ly = gy - wy0;
   if (need && (unsigned)lx < (unsigned)WX && (unsigned)ly < (unsigned)WY) {
     const int k = ly * WX + lx;
@@ -188,20 +203,12 @@ __device__ __forceinline__ void column_values(const StepArgs& A, const FT* s_f, 
     FT f[Q1 * Q1];
 #pragma unroll
     for (int p = 0; p < Q1 * Q1; ++p) f[p] = s_f[p * WN + k];
-    FT h[Q1];
 #pragma unroll
     for (int ip = 0; ip < Q1; ++ip) {
       FT v = FT(0);
 #pragma unroll
       for (int jp = 0; jp < Q1; ++jp) v += gby[jp] * f[ip * Q1 + jp];
-      h[ip] = v;
-    }
-#pragma unroll
-    for (int i = 0; i < Q1; ++i) {
-      FT v = FT(0);
-#pragma unroll
-      for (int ip = 0; ip < Q1; ++ip) v += gbx[i][ip] * h[ip];
-      t[i] = v;
+      hc[ip] += aym * v;
     }
   } else if (need) {
     const size_t plane = (size_t)A.nx * A.ny;
@@ -229,7 +236,7 @@ __device__ __forceinline__ void column_values(const StepArgs& A, const FT* s_f, 
       FT v = FT(0);
 #pragma unroll
       for (int ip = 0; ip < Q1; ++ip) v += FT(gxr[ip]) * h[ip];
-      t[i] = v;
+      acc[i] += (wx[i] * aym) * v;
     }
   }
 }
@@ -487,8 +494,9 @@ k_step(StepArgs A) {
     int tl = tid;
     asm volatile("" : "+v"(tl));
     const int wave = tl >> 6, lane = tl & 63;
-    const int X = bx0 + (wave % (TX / 8)) * 8 + (lane & 7);
-    const int Y = by0 + (wave / (TX / 8)) * 8 + (lane >> 3);
+    constexpr int WTX = TS::WTX, WTY = TS::WTY;
+    const int X = bx0 + (wave % (TX / WTX)) * WTX + (lane % WTX);
+    const int Y = by0 + (wave / (TX / WTX)) * WTY + (lane / WTX);
     const bool active = (X < A.nx) && (Y < A.ny);
     const size_t plane = (size_t)A.nx * A.ny;
     const FT* __restrict__ fin = static_cast<const FT*>(A.f_in);
@@ -560,7 +568,7 @@ k_step(StepArgs A) {
         const int sy = wrap_index(wy0 + wy, A.ny, A.bc_y);
         const size_t src = (size_t)sy * A.nx + sx;
         double f[Q];
-  #pragma unroll
+#pragma unroll
         for (int p = 0; p < Q; ++p) f[p] = double(fin[(size_t)p * plane + src]);
         const double ss = sqrt(gin[2 * plane + src] * L::inv_TL);
         const double r = ss * inv_sB;
@@ -568,21 +576,21 @@ k_step(StepArgs A) {
         transfer_factor<Q1, double>(r, (gin[src] - uxB) * inv_sB, Gx);
         transfer_factor<Q1, double>(r, (gin[plane + src] - uyB) * inv_sB, Gy);
         double Hm[Q];  // Hm[i][l] = sum_j Gy[l][j] f[i][j]
-  #pragma unroll
+#pragma unroll
         for (int i = 0; i < Q1; ++i)
-  #pragma unroll
+#pragma unroll
           for (int l = 0; l < Q1; ++l) {
             double h = 0.0;
-  #pragma unroll
+#pragma unroll
             for (int j = 0; j < Q1; ++j) h = fma(Gy[l * Q1 + j], f[i * Q1 + j], h);
             Hm[i * Q1 + l] = h;
           }
-  #pragma unroll
+#pragma unroll
         for (int kk = 0; kk < Q1; ++kk)
-  #pragma unroll
+#pragma unroll
           for (int l = 0; l < Q1; ++l) {
             double t = 0.0;
-  #pragma unroll
+#pragma unroll
             for (int i = 0; i < Q1; ++i) t = fma(Gx[kk * Q1 + i], Hm[i * Q1 + l], t);
             s_f[(kk * Q1 + l) * WN + k] = FT(t);
           }
@@ -620,7 +628,7 @@ k_step(StepArgs A) {
         FT gbx[Q1][Q1];
         int lo = INT_MAX, hi = INT_MIN;
         bool has = false, far = false;
-  #pragma unroll
+#pragma unroll
         for (int i = 0; i < Q1; ++i) {
           const double xd = double(X) - (s * L::c(i) + ux);
           const double fl = floor(xd);
@@ -628,7 +636,7 @@ k_step(StepArgs A) {
           o[i] = sat_floor(fl) - 1 - X;
           double row[Q1];
           transfer_row<Q1>(i, rB, dBx, row);
-  #pragma unroll
+#pragma unroll
           for (int ip = 0; ip < Q1; ++ip) gbx[i][ip] = FT(row[ip]);
           if (isfinite(xd)) {
             lo = o[i] < lo ? o[i] : lo;
@@ -650,7 +658,7 @@ k_step(StepArgs A) {
         // its y contraction is shared by the four x speeds (each with its own
         // weight, zero where the column is outside that speed's stencil).
         if (!wave_column_range(lo, hi, has, lo, hi)) hi = lo - 1;
-  #pragma unroll 1
+#pragma unroll 1
         for (int j = 0; j < Q1; ++j) {
           // a2 + a3 (y axis): the departure ordinate depends on c_j only.
           const double yd = double(Y) - (s * speed_rt<Q1>(j) + uy);
@@ -662,13 +670,13 @@ k_step(StepArgs A) {
           FT gby[Q1];
           row_to<Q1, FT>(Pj, rB, dBy, gby);
           FT acc_row[Q1];
-  #pragma unroll
+#pragma unroll
           for (int i = 0; i < Q1; ++i) acc_row[i] = FT(0);
-  #pragma unroll 1
+#pragma unroll 1
           for (int rel = lo; rel <= hi; ++rel) {
             FT wx[Q1];
             bool need = false;
-  #pragma unroll
+#pragma unroll
             for (int i = 0; i < Q1; ++i) {
               const int n = rel - o[i];
               const bool in = (unsigned)n < 4u;
@@ -677,28 +685,36 @@ k_step(StepArgs A) {
               need = need || in;
             }
             if (!__any(need)) continue;
-  #pragma unroll 2
+            FT hc[Q1];  // y-contracted window values, summed over the rows
+#pragma unroll
+            for (int ip = 0; ip < Q1; ++ip) hc[ip] = FT(0);
+#pragma unroll 2
             for (int m = 0; m < 4; ++m) {
-              FT t[Q1];
-              column_values<Q1, FT, WX, WY, WN>(A, s_f, wx0, wy0, X + rel, y0 + m, need, gbx, gby,
-                                                Pj, ux, uy, inv_s, t);
               const FT aym = FT(m == 0 ? ay[0] : m == 1 ? ay[1] : m == 2 ? ay[2] : ay[3]);
-  #pragma unroll
-              for (int i = 0; i < Q1; ++i) acc_row[i] += (wx[i] * aym) * t[i];  // a5
+              column_point<Q1, FT, WX, WY, WN>(A, s_f, wx0, wy0, X + rel, y0 + m, need, aym, wx,
+                                               gby, Pj, ux, uy, inv_s, hc, acc_row);
+            }
+            // x rows of G_{B->n}, then the column's x weights (a5)
+#pragma unroll
+            for (int i = 0; i < Q1; ++i) {
+              FT v = FT(0);
+#pragma unroll
+              for (int ip = 0; ip < Q1; ++ip) v += gbx[i][ip] * hc[ip];
+              acc_row[i] += wx[i] * v;
             }
           }
-  #pragma unroll
+#pragma unroll
           for (int i = 0; i < Q1; ++i)
-  #pragma unroll
+#pragma unroll
             for (int jj = 0; jj < Q1; ++jj)
               if (jj == j) ft[i * Q1 + jj] = acc_row[i];
         }
 
         // a6: moments in the peculiar frame of lambda_n (compensated sums).
         FT r0 = 0, r0c = 0, mx = 0, mxc = 0, my = 0, myc = 0, e2 = 0, e2c = 0;
-  #pragma unroll
+#pragma unroll
         for (int i = 0; i < Q1; ++i)
-  #pragma unroll
+#pragma unroll
           for (int j = 0; j < Q1; ++j) {
             const FT fv = ft[i * Q1 + j];
             two_sum_acc(r0, r0c, fv);
@@ -736,23 +752,23 @@ k_step(StepArgs A) {
           transfer_factor<Q1, double>(r, (ux - ux1) * inv_s1, Rx);
           transfer_factor<Q1, double>(r, (uy - uy1) * inv_s1, Ry);
           FT Hm[Q];  // Hm[i][l] = sum_j Ry[l][j] ft[i][j]
-  #pragma unroll
+#pragma unroll
           for (int i = 0; i < Q1; ++i)
-  #pragma unroll
+#pragma unroll
             for (int l = 0; l < Q1; ++l) {
               FT h = FT(0);
-  #pragma unroll
+#pragma unroll
               for (int j = 0; j < Q1; ++j) h += FT(Ry[l * Q1 + j]) * ft[i * Q1 + j];
               Hm[i * Q1 + l] = h;
             }
           // a9: BGK towards rho W (eq. 18), a10: store.
           const FT omega = FT(1.0 / A.tau);
-  #pragma unroll
+#pragma unroll
           for (int k = 0; k < Q1; ++k)
-  #pragma unroll
+#pragma unroll
             for (int l = 0; l < Q1; ++l) {
               FT fr = FT(0);
-  #pragma unroll
+#pragma unroll
               for (int i = 0; i < Q1; ++i) fr += FT(Rx[k * Q1 + i]) * Hm[i * Q1 + l];
               const FT feq = FT(rho1 * (L::w(k) * L::w(l)));
               fout[(size_t)(k * Q1 + l) * plane + node] = fr + omega * (feq - fr);
@@ -799,8 +815,8 @@ k_step(StepArgs A) {
           const unsigned ent = has ? s_list[e] : 0u;
           const int ltid = (int)(ent & 0xFFFF);
           const int lw = ltid >> 6, ll = ltid & 63;
-          const int tX = bx0 + (lw % (TX / 8)) * 8 + (ll & 7);
-          const int tY = by0 + (lw / (TX / 8)) * 8 + (ll >> 3);
+          const int tX = bx0 + (lw % (TX / WTX)) * WTX + (ll % WTX);
+          const int tY = by0 + (lw / (TX / WTX)) * WTY + (ll / WTX);
           double tux = 0.0, tuy = 0.0, tT = L::TL;
           if (has) {
             const size_t tnode = (size_t)tY * A.nx + tX;
@@ -816,7 +832,7 @@ k_step(StepArgs A) {
       }
     }
     if (A.counters) {
-  #pragma unroll
+#pragma unroll
       for (int off = 32; off > 0; off >>= 1) {
         c_nc += __shfl_xor(c_nc, off);
         c_nb += __shfl_xor(c_nb, off);
