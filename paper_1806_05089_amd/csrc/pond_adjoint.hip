@@ -229,31 +229,26 @@ __device__ void forward_pass(const Lane<Q1, FT, WX, WY, WN>& c, const Gauge& G, 
       const bool need = x_column<Q1, false>(x, cc, rel, wx, nullptr);
       if (!__any(need)) continue;
       const int gx = c.X + rel, lx = gx - c.wx0;
+      // window rows: y contraction weighted and summed over the rows, the x
+      // rows of G_{B->n} applied once per column; HBM points point-wise
+      double hc[Q1];
+#pragma unroll
+      for (int ip = 0; ip < Q1; ++ip) hc[ip] = 0.0;
 #pragma unroll 2
       for (int m = 0; m < 4; ++m) {
         const int gy = y0 + m, ly = gy - c.wy0;
-        double t[Q1];
-#pragma unroll
-        for (int i = 0; i < Q1; ++i) t[i] = 0.0;
+        const double aym = pick4(ay, m);
         if (need && (unsigned)lx < (unsigned)WX && (unsigned)ly < (unsigned)WY) {
           const int k = ly * WX + lx;
           double fs[Q1 * Q1];  // all loads first, so that they are in flight together
 #pragma unroll
           for (int p = 0; p < Q1 * Q1; ++p) fs[p] = c.s_fB[p * WN + k];
-          double h[Q1];
 #pragma unroll
           for (int ip = 0; ip < Q1; ++ip) {
             double v = 0.0;
 #pragma unroll
             for (int jp = 0; jp < Q1; ++jp) v = fma(gby[jp], fs[ip * Q1 + jp], v);
-            h[ip] = v;
-          }
-#pragma unroll
-          for (int i = 0; i < Q1; ++i) {
-            double v = 0.0;
-#pragma unroll
-            for (int ip = 0; ip < Q1; ++ip) v = fma(x.gbx[i][ip], h[ip], v);
-            t[i] = v;
+            hc[ip] = fma(aym, v, hc[ip]);
           }
         } else if (need) {
           // outside the window: direct transform G_{s->n} of the HBM state
@@ -281,12 +276,16 @@ __device__ void forward_pass(const Lane<Q1, FT, WX, WY, WN>& c, const Gauge& G, 
             double v = 0.0;
 #pragma unroll
             for (int ip = 0; ip < Q1; ++ip) v = fma(gxr[ip], h[ip], v);
-            t[i] = v;
+            acc[i] = fma(wx[i] * aym, v, acc[i]);
           }
         }
-        const double aym = pick4(ay, m);
+      }
 #pragma unroll
-        for (int i = 0; i < Q1; ++i) acc[i] = fma(wx[i] * aym, t[i], acc[i]);
+      for (int i = 0; i < Q1; ++i) {
+        double v = 0.0;
+#pragma unroll
+        for (int ip = 0; ip < Q1; ++ip) v = fma(x.gbx[i][ip], hc[ip], v);
+        acc[i] = fma(wx[i], v, acc[i]);
       }
     }
 #pragma unroll
