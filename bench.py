@@ -38,6 +38,7 @@ FLOPS_PER_NODE_PASS = 16 * 16 * 42 + 16 * 16 * 64
 FLOPS_PER_NODE_STEP = 560
 PEAK_FP64_TFLOPS = 78.6   # MI355X vector FP64: 256 CU x 2.4 GHz x 64 lanes x 2
 PEAK_FP32_TFLOPS = 157.3  # MI355X published FP32 peak
+PEAK_HBM_GBPS = 8000.0    # MI355X HBM3E
 STEP_SOURCE = os.path.join(ROOT, "paper_1806_05089_amd", "csrc", "pond_step.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_riemann2d_1024_fp64_hbm_traffic.json")
 
@@ -180,6 +181,77 @@ def field_errors(cfg64, s64, cfg32, s32):
     return out
 
 
+def fp32_error_by_step(w, steps=(10, 100)):
+    """FP32-mixed vs FP64 per-field error after n steps from the initial state."""
+    c64, c32 = make_cfg(w, pond.POND_F64), make_cfg(w, pond.POND_F32_MIXED)
+    a64 = pond.init(c64, w.rho, w.ux, w.uy, w.T)
+    a32 = pond.init(c32, w.rho, w.ux, w.uy, w.T)
+    out, done = {}, 0
+    for n in steps:
+        a64, _ = pond.step(c64, a64, nsteps=n - done)
+        a32, _ = pond.step(c32, a32, nsteps=n - done)
+        done = n
+        out[f"step_{n}"] = field_errors(c64, a64, c32, a32)
+    return out
+
+
+def fp32_error_other_configs():
+    """FP32-mixed vs FP64 per-field error at the end of the shock tube (1024 x 4,
+    400 steps) and the Mach 5 flow (256^2, 1000 steps)."""
+    res = {}
+    for name, w, n in (("sod_1024x4_400_steps", workloads.sod(1024, 4), 400),
+                       ("mach5_256_1000_steps", workloads.mach5(256, seed=0), 1000)):
+        c64, c32 = make_cfg(w, pond.POND_F64), make_cfg(w, pond.POND_F32_MIXED)
+        o64, _ = pond.step(c64, pond.init(c64, w.rho, w.ux, w.uy, w.T), nsteps=n)
+        o32, _ = pond.step(c32, pond.init(c32, w.rho, w.ux, w.uy, w.T), nsteps=n)
+        res[name] = field_errors(c64, o64, c32, o32)
+    return res
+
+
+def riemann_2048(steps=200, warmup=2):
+    """FP64 and FP32-mixed throughput on the 2048^2 Riemann problem (first steps)."""
+    w = workloads.riemann2d(2048, seed=3)
+    nodes = 2048 * 2048
+    out = {}
+    for name, prec in (("f64", pond.POND_F64), ("f32_mixed", pond.POND_F32_MIXED)):
+        ms, _, _ = timed_steps(make_cfg(w, prec), w, steps, warmup)
+        out[name] = {"value": nodes * steps / (ms * 1e-3) / 1e6, "unit": "MLUPS",
+                     "ms_per_step": ms / steps}
+    out["speedup_fp32_vs_fp64"] = out["f32_mixed"]["value"] / out["f64"]["value"]
+    out["steps"] = steps
+    return out
+
+
+def cpu_single_thread(cfg, state, sample_nodes=40000, seed=1):
+    import oracle
+    prev = oracle.set_num_threads(1)
+    try:
+        r = cpu_baseline(cfg, state, sample_nodes, seed)
+    finally:
+        oracle.set_num_threads(prev)
+    return r
+
+
+def cpu_small_configs():
+    """The oracle on the Taylor-Green run (32^2, all 200 steps) and on the first
+    40 of the shock tube's 400 steps (1024 x 4; the oracle parallelises over
+    rows, so this tube keeps only 4 threads busy), all host threads."""
+    import oracle
+    out = {}
+    for name, w, n in (("taylor_green_32_200_steps", workloads.taylor_green(32), 200),
+                       ("sod_1024x4_first_40_steps", workloads.sod(1024, 4), 40)):
+        oc = oracle.OracleConfig(q=4, isothermal=w.isothermal, bc_x=w.bc_x, bc_y=w.bc_y,
+                                 max_iter=20, tau=w.tau)
+        f, g = oracle.init(w.rho, w.ux, w.uy, w.T, q=4)
+        t = time.perf_counter()
+        for _ in range(n):
+            f, g, _, _ = oracle.step(f, g, oc)
+        dt = time.perf_counter() - t
+        out[name] = {"value": w.rho.size * n / dt / 1e6, "unit": "MLUPS", "seconds": dt}
+    out["cores"] = oracle.num_threads()
+    return out
+
+
 def traffic_per_launch(n_launch_nodes):
     """HBM bytes per step launch from the committed counter summary, if it was
     taken on the current step kernel source; else None."""
@@ -266,12 +338,17 @@ def main():
         achieved = flops / (ms64 / args.steps * 1e-3) / 1e12
         result["mean_pc_passes"] = passes64["mean_passes"]
         result["nonconverged_node_steps"] = passes64["nonconverged_node_steps"]
+        traffic = traffic_per_launch(nodes)
         result["roofline"] = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
                               "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
-                              "traffic": traffic_per_launch(nodes),
+                              "traffic": traffic,
                               "kernel": "k_step<4,double,32,16,5>",
                               "flops_per_node_pass": FLOPS_PER_NODE_PASS,
                               "flops_per_launch": flops}
+        if traffic:
+            gbps = traffic / (ms64 / args.steps * 1e-3) / 1e9
+            result["roofline"]["hbm_GBps"] = gbps
+            result["roofline"]["hbm_frac"] = gbps / PEAK_HBM_GBPS
 
     if not args.no_fp32:
         cfg32 = make_cfg(w, pond.POND_F32_MIXED)
@@ -291,7 +368,11 @@ def main():
             a32 = flops / (ms32 / args.steps * 1e-3) / 1e12
             fp32["roofline"] = {"bound": "alu", "achieved": a32, "peak": PEAK_FP32_TFLOPS,
                                 "unit": "TFLOP/s", "frac": a32 / PEAK_FP32_TFLOPS}
+        log("[bench] FP32-mixed error by step and on the other configs; 2048^2")
+        fp32["error_vs_fp64_by_step"] = fp32_error_by_step(w)
+        fp32["error_vs_fp64_other_configs"] = fp32_error_other_configs()
         result["fp32_mixed"] = fp32
+        result["riemann2d_2048"] = riemann_2048()
 
     if not args.no_adjoint:
         log("[bench] adjoint / forward")
@@ -303,6 +384,8 @@ def main():
     if not args.no_cpu_baseline:
         log("[bench] oracle on host cores")
         result["cpu_baseline"] = cpu_baseline(cfg64, s64, args.cpu_sample)
+        result["cpu_baseline"]["single_thread"] = cpu_single_thread(cfg64, s64)
+        result["cpu_baseline"]["whole_runs"] = cpu_small_configs()
     print(json.dumps(result), flush=True)
 
 

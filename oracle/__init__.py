@@ -22,6 +22,7 @@ from ._binding import (  # noqa: F401
     step_cs,
     moments_cs,
     num_threads,
+    set_num_threads,
     OracleConfig,
     library_path,
 )

@@ -41,6 +41,8 @@ def _load():
     lib.oracle_step_cs.argtypes = cfg + [D, D, D, D] + [_dp] * 8 + [_ip, _ip]
     lib.oracle_moments_cs.argtypes = [I, I, I] + [_dp] * 12
     lib.oracle_num_threads.restype = I
+    lib.oracle_set_num_threads.argtypes = [I]
+    lib.oracle_set_num_threads.restype = I
     _lib = lib
     return lib
 
@@ -76,6 +78,11 @@ class OracleConfig:
 
 def num_threads() -> int:
     return _load().oracle_num_threads()
+
+
+def set_num_threads(n: int) -> int:
+    """Threads for the following oracle calls; returns the previous count."""
+    return _load().oracle_set_num_threads(int(n))
 
 
 def lattice(q: int = 4):

@@ -582,4 +582,13 @@ int oracle_num_threads(void) {
 #endif
 }
 
+// Threads of the following calls (n >= 1); returns the previous count.
+int oracle_set_num_threads(int n) {
+  const int prev = oracle_num_threads();
+#ifdef _OPENMP
+  if (n >= 1) omp_set_num_threads(n);
+#endif
+  return prev;
+}
+
 }  // extern "C"
