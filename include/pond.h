@@ -23,6 +23,15 @@
  *   - Physical failures inside a step (no convergence, T <= 0, rho <= 0,
  *     non-finite values) are not errors: they are counted in pond_stats and
  *     marked in the per-node iteration plane.
+ *   - Library-held device memory: the first pond_init / pond_step /
+ *     pond_step_adjoint on a (device, stream) pair allocates and zeroes a small
+ *     slot for it (step statistics, the step kernel's tile queue, and one cost
+ *     key and one order entry per 32 x 16 tile, grown after a stream
+ *     synchronisation when a larger grid appears); it is held until the
+ *     process ends.  A step leaves its tiles' costs there, and the next step
+ *     on the same stream takes the costliest tiles first; results do not
+ *     depend on that order.  Calls on one stream run in order; concurrent
+ *     calls on different streams use different slots.
  */
 #ifndef POND_H_
 #define POND_H_
