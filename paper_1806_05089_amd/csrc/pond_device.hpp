@@ -208,6 +208,15 @@ __device__ __forceinline__ bool wave_column_range(int lo, int hi, bool has, int&
 // lies further than this from its node is handled on its own instead.
 constexpr int kFarColumns = 256;
 
+// Weight of stencil node n (0..3) alone: the same products as interp_weights.
+__device__ __forceinline__ double interp_weight_at(int n, double t) {
+  const double e1 = t - (n == 0 ? 1.0 : 0.0);
+  const double e2 = t - (n <= 1 ? 2.0 : 1.0);
+  const double e3 = t - (n <= 2 ? 3.0 : 2.0);
+  const double cn = n == 0 ? -1.0 / 6.0 : n == 1 ? 0.5 : n == 2 ? -0.5 : 1.0 / 6.0;
+  return e1 * e2 * e3 * cn;
+}
+
 // Stencil index -> node index: periodic wrap or zero-gradient clamp.
 __device__ __forceinline__ int wrap_index(int i, int n, int bc) {
   if (bc == 0) {

@@ -624,7 +624,7 @@ k_step(StepArgs A) {
         // a2 + a3 (x axis) for every x speed: departure columns x0_i (as offsets
         // o_i = x0_i - X), weights, and the rows of G_{B->n} along x.
         int o[Q1];
-        double ax[Q1][4];
+        double tx[Q1];  // departure coordinate in its stencil (weights per column)
         FT gbx[Q1][Q1];
         int lo = INT_MAX, hi = INT_MIN;
         bool has = false, far = false;
@@ -632,7 +632,7 @@ k_step(StepArgs A) {
         for (int i = 0; i < Q1; ++i) {
           const double xd = double(X) - (s * L::c(i) + ux);
           const double fl = floor(xd);
-          interp_weights(xd - (fl - 1.0), ax[i]);
+          tx[i] = xd - (fl - 1.0);
           o[i] = sat_floor(fl) - 1 - X;
           double row[Q1];
           transfer_row<Q1>(i, rB, dBx, row);
@@ -680,8 +680,7 @@ k_step(StepArgs A) {
             for (int i = 0; i < Q1; ++i) {
               const int n = rel - o[i];
               const bool in = (unsigned)n < 4u;
-              const double a = n == 0 ? ax[i][0] : n == 1 ? ax[i][1] : n == 2 ? ax[i][2] : ax[i][3];
-              wx[i] = in ? FT(a) : FT(0);
+              wx[i] = in ? FT(interp_weight_at(n, tx[i])) : FT(0);
               need = need || in;
             }
             if (!__any(need)) continue;
