@@ -663,8 +663,9 @@ k_step(StepArgs A) {
           // a2 + a3 (y axis): the departure ordinate depends on c_j only.
           const double yd = double(Y) - (s * speed_rt<Q1>(j) + uy);
           const double fly = floor(yd);
+          const double ty = yd - (fly - 1.0);
           double ay[4];
-          interp_weights(yd - (fly - 1.0), ay);
+          interp_weights(ty, ay);
           const int y0 = sat_floor(fly) - 1;
           const LagRow Pj = lag_row<Q1>(j);
           FT gby[Q1];
@@ -687,11 +688,20 @@ k_step(StepArgs A) {
             FT hc[Q1];  // y-contracted window values, summed over the rows
 #pragma unroll
             for (int ip = 0; ip < Q1; ++ip) hc[ip] = FT(0);
+            if constexpr (sizeof(FT) == 8) {
+              // FP64: rows unrolled, weights from their constant node index
+#pragma unroll
+              for (int m = 0; m < 4; ++m)
+                column_point<Q1, FT, WX, WY, WN>(A, s_f, wx0, wy0, X + rel, y0 + m, need,
+                                                 FT(interp_weight_at(m, ty)), wx, gby, Pj, ux,
+                                                 uy, inv_s, hc, acc_row);
+            } else {
 #pragma unroll 2
-            for (int m = 0; m < 4; ++m) {
-              const FT aym = FT(m == 0 ? ay[0] : m == 1 ? ay[1] : m == 2 ? ay[2] : ay[3]);
-              column_point<Q1, FT, WX, WY, WN>(A, s_f, wx0, wy0, X + rel, y0 + m, need, aym, wx,
-                                               gby, Pj, ux, uy, inv_s, hc, acc_row);
+              for (int m = 0; m < 4; ++m) {
+                const FT aym = FT(m == 0 ? ay[0] : m == 1 ? ay[1] : m == 2 ? ay[2] : ay[3]);
+                column_point<Q1, FT, WX, WY, WN>(A, s_f, wx0, wy0, X + rel, y0 + m, need, aym,
+                                                 wx, gby, Pj, ux, uy, inv_s, hc, acc_row);
+              }
             }
             // x rows of G_{B->n}, then the column's x weights (a5)
 #pragma unroll
