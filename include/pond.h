@@ -32,6 +32,10 @@
  *     on the same stream takes the costliest tiles first; results do not
  *     depend on that order.  Calls on one stream run in order; concurrent
  *     calls on different streams use different slots.
+ *   - HIP graph capture: pond_step (without stats) and pond_step_adjoint
+ *     record kernels and device copies only, no memset.  Make one call on the
+ *     capturing stream before capture (it allocates the stream's slot) and
+ *     capture at most the grid size used then.
  */
 #ifndef POND_H_
 #define POND_H_
