@@ -13,6 +13,7 @@ host cores (`cpu_baseline`) are reported beside it.
 Other modes (used for profiling, each prints its own line):
   --kernel-only   FP64 steps only, no replays or baselines (for rocprofv3)
   --copy-probe    a plain device copy of known size (HBM counter calibration)
+  --adjoint-only  FP64 adjoint of one step at the state after 50 steps, twice
 """
 import argparse
 import hashlib
@@ -263,6 +264,28 @@ def traffic_per_launch(n_launch_nodes):
     return rec.get("bytes_per_launch")
 
 
+def adjoint_only(size, reps=2):
+    """pond_step_adjoint about one step of the Riemann problem after 50 steps."""
+    w = workloads.riemann2d(size, seed=3)
+    cfg = make_cfg(w, pond.POND_F64)
+    a = pond.init(cfg, w.rho, w.ux, w.uy, w.T)
+    a, _ = pond.step(cfg, a, nsteps=50)
+    out, _ = pond.step(cfg, a)
+    g = torch.Generator(device="cuda").manual_seed(0)
+    wf = torch.randn(out.f.shape, dtype=torch.float64, device="cuda", generator=g)
+    wg = torch.randn(out.g.shape, dtype=torch.float64, device="cuda", generator=g)
+    atau = torch.zeros(1, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        pond.step_adjoint(cfg, a, out, wf, wg, atau)
+    e1.record()
+    torch.cuda.synchronize()
+    print(json.dumps({"adjoint_only": True, "ms_per_call": e0.elapsed_time(e1) / reps}), flush=True)
+
+
 def copy_probe():
     n = 1 << 27  # 1 GiB of float64
     a = torch.ones(n, dtype=torch.float64, device="cuda")
@@ -287,6 +310,7 @@ def main():
     p.add_argument("--no-pass-count", action="store_true")
     p.add_argument("--kernel-only", action="store_true")
     p.add_argument("--copy-probe", action="store_true")
+    p.add_argument("--adjoint-only", action="store_true")
     args = p.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the PonD step here has no multi-GPU path "
@@ -298,6 +322,9 @@ def main():
         sys.exit(2)
     if args.copy_probe:
         copy_probe()
+        return
+    if args.adjoint_only:
+        adjoint_only(args.size)
         return
 
     w = workloads.riemann2d(args.size, seed=3)
