@@ -234,10 +234,10 @@ __device__ void forward_pass(const Lane<Q1, FT, WX, WY, WN>& c, const Gauge& G, 
       double hc[Q1];
 #pragma unroll
       for (int ip = 0; ip < Q1; ++ip) hc[ip] = 0.0;
-#pragma unroll 2
+#pragma unroll
       for (int m = 0; m < 4; ++m) {
         const int gy = y0 + m, ly = gy - c.wy0;
-        const double aym = pick4(ay, m);
+        const double aym = pick4(ay, m);  // constant index once unrolled
         if (need && (unsigned)lx < (unsigned)WX && (unsigned)ly < (unsigned)WY) {
           const int k = ly * WX + lx;
           double fs[Q1 * Q1];  // all loads first, so that they are in flight together
@@ -353,10 +353,10 @@ __device__ void adjoint_pass(const Lane<Q1, FT, WX, WY, WN>& c, const Gauge& G, 
         colv[i] = 0.0;
         dcol[i] = 0.0;
       }
-#pragma unroll 1
+#pragma unroll
       for (int m = 0; m < 4; ++m) {
         const int gy = y0 + m, ly = gy - c.wy0;
-        const double aym = pick4(ay, m), daym = pick4(day, m);
+        const double aym = pick4(ay, m), daym = pick4(day, m);  // constant index once unrolled
         double cw[Q1], val[Q1];
 #pragma unroll
         for (int i = 0; i < Q1; ++i) {
