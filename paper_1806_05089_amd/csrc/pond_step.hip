@@ -1,9 +1,7 @@
 // The fused PonD time step on gfx950: propagation with the predictor-corrector
 // gauge iteration (eqs. 6-16, App. E), regauge and BGK collision (eqs. 17-18).
 //
-// Mapping.  One lane owns one node; a wave covers an 8 x 8 tile of nodes
-// (nodes that need many predictor-corrector passes cluster along fronts, and
-// square wave tiles cut the number of waves a front crosses).
+// Mapping.  One lane owns one node; a wave covers a 32 x 2 tile of nodes.
 //
 // Common-frame halo window.  A block of TX x TY nodes stages a
 // (TX + 2H) x (TY + 2H) window of the state at t - dt in LDS, placed around the
@@ -14,8 +12,10 @@
 // (G_{B->n} G_{s->B} = G_{s->n}), so inside the pass loop the transform of a
 // collocation point s into the node's gauge lambda_n is G_{B->n} applied to
 // the staged f^B_s: the per-axis factors of G_{B->n} are built once per node
-// and pass, and a (population, collocation point) pair costs 16 LDS reads and
-// 20 multiply-adds.  A collocation point outside the window is read from HBM
+// and pass.  A wave walks the union of its lanes' stencil columns (relative
+// to each lane's node) once per y speed; a column's four rows are read from
+// LDS once, contracted with the y row of G_{B->n} and summed with their y
+// weights, and the four x speeds share the result.  A collocation point outside the window is read from HBM
 // and transformed directly with G_{s->n}.  After staging the lanes iterate
 // independently (no further barriers).
 #include <hip/hip_runtime.h>
@@ -25,17 +25,10 @@
 #include "pond_device.hpp"
 #include "pond_internal.hpp"
 
-// Width of a wave's node tile (64 / width rows).  FP64: 8 x 8 (square tiles
-// cut the number of waves a front of slow-converging nodes crosses).  FP32:
-// 32 x 2, whose LDS reads of a collocation point are free of bank conflicts
-// (8 x 8 tiles spend half the LDS cycles in conflicts, which only the FP32
-// kernel feels).
-#ifndef POND_WAVE_TX_F64
-#define POND_WAVE_TX_F64 8
-#endif
-#ifndef POND_WAVE_TX_F32
-#define POND_WAVE_TX_F32 32
-#endif
+// A wave's node tile is 32 x 2: the lanes of a wave read a collocation point
+// from 32 consecutive window columns of two rows, free of LDS bank conflicts
+// (8 x 8 tiles spend about half of the LDS cycles in conflicts).
+constexpr int kWaveTX = 32;
 
 namespace pond {
 namespace {
@@ -48,7 +41,7 @@ struct TileShape {
   static constexpr int NT = TX * TY;
   static constexpr int NW = NT / 64;
   static constexpr size_t lds_bytes = (size_t)Q1 * Q1 * WN * sizeof(FT);
-  static constexpr int WTX = sizeof(FT) == 8 ? POND_WAVE_TX_F64 : POND_WAVE_TX_F32;
+  static constexpr int WTX = kWaveTX;
   static constexpr int WTY = 64 / WTX;  // wave tile
   static_assert(TX % WTX == 0 && TY % WTY == 0, "waves tile the block");
   static_assert(lds_bytes + 1024 <= 160 * 1024, "window exceeds the 160 KiB LDS of a CU");
@@ -237,6 +230,40 @@ __device__ __forceinline__ void column_point(const StepArgs& A, const FT* s_f, i
 #pragma unroll
       for (int ip = 0; ip < Q1; ++ip) v += FT(gxr[ip]) * h[ip];
       acc[i] += (wx[i] * aym) * v;
+    }
+  }
+}
+
+// a4 + a5 on the LDS window for the four rows of one stencil column, the
+// lane's whole column inside the window (index k of its first row): the y
+// contractions with the G_{B->n} row gby, weighted by ayw and summed into hc.
+// The planes are addressed from two bases (planes below and above Q/2) so
+// that every load takes its plane and row from the 16-bit instruction offset.
+// In FP64 each row's loads are kept with their row: left free, the scheduler
+// pairs the rows into ds_read2_b64 and holds all 4 x Q values of the column
+// at once, which measured slower; FP32 gains from the pairing.
+template <int Q1, class FT, int WX, int WN>
+__device__ __forceinline__ void window_column(const FT* s_f, int k, const FT* ayw, const FT* gby,
+                                              FT* hc) {
+  constexpr int Q = Q1 * Q1, QH = Q / 2;
+  int kh = k + QH * WN;
+  asm volatile("" : "+v"(kh));
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    FT f[Q];
+#pragma unroll
+    for (int p = 0; p < QH; ++p) f[p] = s_f[k + p * WN + m * WX];
+#pragma unroll
+    for (int p = QH; p < Q; ++p) f[p] = s_f[kh + (p - QH) * WN + m * WX];
+#pragma unroll
+    for (int ip = 0; ip < Q1; ++ip) {
+      FT v = FT(0);
+#pragma unroll
+      for (int jp = 0; jp < Q1; ++jp) v += gby[jp] * f[ip * Q1 + jp];
+      hc[ip] += ayw[m] * v;
+    }
+    if constexpr (sizeof(FT) == 8) {
+      if (m < 3) __builtin_amdgcn_sched_barrier(0);
     }
   }
 }
@@ -664,9 +691,12 @@ k_step(StepArgs A) {
           const double yd = double(Y) - (s * speed_rt<Q1>(j) + uy);
           const double fly = floor(yd);
           const double ty = yd - (fly - 1.0);
-          double ay[4];
-          interp_weights(ty, ay);
+          FT ayw[4];
+#pragma unroll
+          for (int m = 0; m < 4; ++m) ayw[m] = FT(interp_weight_at(m, ty));
           const int y0 = sat_floor(fly) - 1;
+          const int ly0 = y0 - wy0;
+          const bool rows_in = (unsigned)ly0 <= (unsigned)(WY - 4);
           const LagRow Pj = lag_row<Q1>(j);
           FT gby[Q1];
           row_to<Q1, FT>(Pj, rB, dBy, gby);
@@ -688,18 +718,15 @@ k_step(StepArgs A) {
             FT hc[Q1];  // y-contracted window values, summed over the rows
 #pragma unroll
             for (int ip = 0; ip < Q1; ++ip) hc[ip] = FT(0);
-            if constexpr (sizeof(FT) == 8) {
-              // FP64: rows unrolled, weights from their constant node index
-#pragma unroll
-              for (int m = 0; m < 4; ++m)
-                column_point<Q1, FT, WX, WY, WN>(A, s_f, wx0, wy0, X + rel, y0 + m, need,
-                                                 FT(interp_weight_at(m, ty)), wx, gby, Pj, ux,
-                                                 uy, inv_s, hc, acc_row);
-            } else {
-#pragma unroll 2
+            const int lx = X + rel - wx0;
+            if (need && rows_in && (unsigned)lx < (unsigned)WX) {
+              window_column<Q1, FT, WX, WN>(s_f, ly0 * WX + lx, ayw, gby, hc);
+            } else if (need) {
+              // a column that leaves the window: point by point, LDS or HBM
+#pragma unroll 1
               for (int m = 0; m < 4; ++m) {
-                const FT aym = FT(m == 0 ? ay[0] : m == 1 ? ay[1] : m == 2 ? ay[2] : ay[3]);
-                column_point<Q1, FT, WX, WY, WN>(A, s_f, wx0, wy0, X + rel, y0 + m, need, aym,
+                const FT aym = m == 0 ? ayw[0] : m == 1 ? ayw[1] : m == 2 ? ayw[2] : ayw[3];
+                column_point<Q1, FT, WX, WY, WN>(A, s_f, wx0, wy0, X + rel, y0 + m, true, aym,
                                                  wx, gby, Pj, ux, uy, inv_s, hc, acc_row);
               }
             }
