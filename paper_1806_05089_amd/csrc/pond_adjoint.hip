@@ -197,14 +197,71 @@ __device__ __forceinline__ double pick4(const double* a, int m) {
   return m == 0 ? a[0] : m == 1 ? a[1] : m == 2 ? a[2] : a[3];
 }
 
-// Forward pass at gauge G: F[i*Q1+j] = advected populations (eqs. 5-6),
-// column by column as in the forward step (one read of each collocation
-// point per y speed, its y contraction shared by the x speeds).
+// Window part of a forward collocation point (LDS index k; planes below Q/2
+// from k, the others from kh = k + Q/2 WN): the y contraction with the
+// G_{B->n} row gby, weighted by aym and added to hc.
+template <int Q1, int WN>
+__device__ __forceinline__ void fwd_window_point(const double* s_fB, int k, int kh, double aym,
+                                                 const double* gby, double* hc) {
+  constexpr int Q = Q1 * Q1, QH = Q / 2;
+  double fs[Q];  // all loads first, so that they are in flight together
+#pragma unroll
+  for (int p = 0; p < QH; ++p) fs[p] = s_fB[k + p * WN];
+#pragma unroll
+  for (int p = QH; p < Q; ++p) fs[p] = s_fB[kh + (p - QH) * WN];
+#pragma unroll
+  for (int ip = 0; ip < Q1; ++ip) {
+    double v = 0.0;
+#pragma unroll
+    for (int jp = 0; jp < Q1; ++jp) v = fma(gby[jp], fs[ip * Q1 + jp], v);
+    hc[ip] = fma(aym, v, hc[ip]);
+  }
+}
+
+// A forward collocation point outside the window: direct transform G_{s->n}
+// of the HBM state at (gx, gy), added to acc with the weights wx[i] * aym.
 template <int Q1, class FT, int WX, int WY, int WN>
-__device__ void forward_pass(const Lane<Q1, FT, WX, WY, WN>& c, const Gauge& G, double* F) {
+__device__ __forceinline__ void fwd_hbm_point(const Lane<Q1, FT, WX, WY, WN>& c, const Gauge& G,
+                                              int gx, int gy, double aym, const double* wx,
+                                              const LagRow& Pj, double inv_s, double* acc) {
   using L = Lat<Q1>;
   const AdjArgs& A = *c.A;
   const FT* __restrict__ fin = static_cast<const FT*>(A.f_in);
+  const size_t src = (size_t)wrap_index(gy, A.ny, A.bc_y) * A.nx + wrap_index(gx, A.nx, A.bc_x);
+  double fs[Q1 * Q1];
+#pragma unroll
+  for (int p = 0; p < Q1 * Q1; ++p) fs[p] = double(fin[(size_t)p * c.plane + src]);
+  const double r = sqrt(A.g_in[2 * c.plane + src] * L::inv_TL) * inv_s;
+  const double dx = (A.g_in[src] - G.ux) * inv_s;
+  double gyr[Q1];
+  transfer_row_coef<Q1>(Pj, r, (A.g_in[c.plane + src] - G.uy) * inv_s, gyr);
+  double h[Q1];
+#pragma unroll
+  for (int ip = 0; ip < Q1; ++ip) {
+    double v = 0.0;
+#pragma unroll
+    for (int jp = 0; jp < Q1; ++jp) v = fma(gyr[jp], fs[ip * Q1 + jp], v);
+    h[ip] = v;
+  }
+#pragma unroll
+  for (int i = 0; i < Q1; ++i) {
+    double gxr[Q1];
+    transfer_row<Q1>(i, r, dx, gxr);
+    double v = 0.0;
+#pragma unroll
+    for (int ip = 0; ip < Q1; ++ip) v = fma(gxr[ip], h[ip], v);
+    acc[i] = fma(wx[i] * aym, v, acc[i]);
+  }
+}
+
+// Forward pass at gauge G: F[i*Q1+j] = advected populations (eqs. 5-6),
+// column by column as in the forward step (one read of each collocation
+// point per y speed, its y contraction shared by the x speeds).  A lane whose
+// four rows of the column lie in the window takes them in one straight run;
+// otherwise point by point, from LDS or HBM.
+template <int Q1, class FT, int WX, int WY, int WN>
+__device__ void forward_pass(const Lane<Q1, FT, WX, WY, WN>& c, const Gauge& G, double* F) {
+  constexpr int QH = Q1 * Q1 / 2;
   const double inv_s = 1.0 / G.s;
   const double rB = c.sB * inv_s, dBx = (c.uxB - G.ux) * inv_s, dBy = (c.uyB - G.uy) * inv_s;
   XAxis<Q1> x;
@@ -216,6 +273,8 @@ __device__ void forward_pass(const Lane<Q1, FT, WX, WY, WN>& c, const Gauge& G, 
     double ay[4];
     interp_weights(yd - (fly - 1.0), ay);
     const int y0 = sat_floor_a(fly) - 1;
+    const int ly0 = y0 - c.wy0;
+    const bool rows_in = (unsigned)ly0 <= (unsigned)(WY - 4);
     const LagRow Pj = lag_row<Q1>(j);
     double gby[Q1];
     transfer_row_coef<Q1>(Pj, rB, dBy, gby);
@@ -234,49 +293,23 @@ __device__ void forward_pass(const Lane<Q1, FT, WX, WY, WN>& c, const Gauge& G, 
       double hc[Q1];
 #pragma unroll
       for (int ip = 0; ip < Q1; ++ip) hc[ip] = 0.0;
+      if (need && rows_in && (unsigned)lx < (unsigned)WX) {
+        const int k = ly0 * WX + lx;
+        int kh = k + QH * WN;
+        asm volatile("" : "+v"(kh));
 #pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        const int gy = y0 + m, ly = gy - c.wy0;
-        const double aym = pick4(ay, m);  // constant index once unrolled
-        if (need && (unsigned)lx < (unsigned)WX && (unsigned)ly < (unsigned)WY) {
-          const int k = ly * WX + lx;
-          double fs[Q1 * Q1];  // all loads first, so that they are in flight together
-#pragma unroll
-          for (int p = 0; p < Q1 * Q1; ++p) fs[p] = c.s_fB[p * WN + k];
-#pragma unroll
-          for (int ip = 0; ip < Q1; ++ip) {
-            double v = 0.0;
-#pragma unroll
-            for (int jp = 0; jp < Q1; ++jp) v = fma(gby[jp], fs[ip * Q1 + jp], v);
-            hc[ip] = fma(aym, v, hc[ip]);
-          }
-        } else if (need) {
-          // outside the window: direct transform G_{s->n} of the HBM state
-          const size_t src =
-              (size_t)wrap_index(gy, A.ny, A.bc_y) * A.nx + wrap_index(gx, A.nx, A.bc_x);
-          double fs[Q1 * Q1];
-#pragma unroll
-          for (int p = 0; p < Q1 * Q1; ++p) fs[p] = double(fin[(size_t)p * c.plane + src]);
-          const double r = sqrt(A.g_in[2 * c.plane + src] * L::inv_TL) * inv_s;
-          const double dx = (A.g_in[src] - G.ux) * inv_s;
-          double gyr[Q1];
-          transfer_row_coef<Q1>(Pj, r, (A.g_in[c.plane + src] - G.uy) * inv_s, gyr);
-          double h[Q1];
-#pragma unroll
-          for (int ip = 0; ip < Q1; ++ip) {
-            double v = 0.0;
-#pragma unroll
-            for (int jp = 0; jp < Q1; ++jp) v = fma(gyr[jp], fs[ip * Q1 + jp], v);
-            h[ip] = v;
-          }
-#pragma unroll
-          for (int i = 0; i < Q1; ++i) {
-            double gxr[Q1];
-            transfer_row<Q1>(i, r, dx, gxr);
-            double v = 0.0;
-#pragma unroll
-            for (int ip = 0; ip < Q1; ++ip) v = fma(gxr[ip], h[ip], v);
-            acc[i] = fma(wx[i] * aym, v, acc[i]);
+        for (int m = 0; m < 4; ++m)
+          fwd_window_point<Q1, WN>(c.s_fB, k + m * WX, kh + m * WX, pick4(ay, m), gby, hc);
+      } else if (need) {
+#pragma unroll 1
+        for (int m = 0; m < 4; ++m) {
+          const int gy = y0 + m, ly = gy - c.wy0;
+          const double aym = pick4(ay, m);
+          if ((unsigned)lx < (unsigned)WX && (unsigned)ly < (unsigned)WY) {
+            const int k = ly * WX + lx;
+            fwd_window_point<Q1, WN>(c.s_fB, k, k + QH * WN, aym, gby, hc);
+          } else {
+            fwd_hbm_point<Q1, FT, WX, WY, WN>(c, G, gx, gy, aym, wx, Pj, inv_s, acc);
           }
         }
       }
@@ -296,6 +329,145 @@ __device__ void forward_pass(const Lane<Q1, FT, WX, WY, WN>& c, const Gauge& G, 
   }
 }
 
+// Adjoint of a window collocation point (LDS index k; planes below Q/2 from
+// k, the others from kh = k + Q/2 WN) for one row: val[i] = x speed i's
+// transformed value (before weights), cotangents of the G_{B->n} rows
+// accumulated in gbx_bar / gby_bar, and the cotangent of the staged
+// populations scattered into the LDS accumulators.  cw[i] is the cotangent
+// of the point's contribution to x speed i.
+template <int Q1, int WN>
+__device__ __forceinline__ void adj_window_point(const double* s_fB, double* s_acc, int k, int kh,
+                                                 const double* gby, const double (*gbx)[Q1],
+                                                 const double* cw, double* val,
+                                                 double (*gbx_bar)[Q1], double* gby_bar) {
+  constexpr int Q = Q1 * Q1, QH = Q / 2;
+  double fs[Q];
+#pragma unroll
+  for (int p = 0; p < QH; ++p) fs[p] = s_fB[k + p * WN];
+#pragma unroll
+  for (int p = QH; p < Q; ++p) fs[p] = s_fB[kh + (p - QH) * WN];
+  double h[Q1], U[Q1];
+#pragma unroll
+  for (int ip = 0; ip < Q1; ++ip) {
+    double v = 0.0;
+#pragma unroll
+    for (int jp = 0; jp < Q1; ++jp) v = fma(gby[jp], fs[ip * Q1 + jp], v);
+    h[ip] = v;
+    double u = 0.0;
+#pragma unroll
+    for (int i = 0; i < Q1; ++i) u = fma(cw[i], gbx[i][ip], u);
+    U[ip] = u;
+  }
+#pragma unroll
+  for (int i = 0; i < Q1; ++i) {
+    double v = 0.0;
+#pragma unroll
+    for (int ip = 0; ip < Q1; ++ip) {
+      v = fma(gbx[i][ip], h[ip], v);
+      gbx_bar[i][ip] = fma(cw[i], h[ip], gbx_bar[i][ip]);
+    }
+    val[i] = v;
+  }
+#pragma unroll
+  for (int jp = 0; jp < Q1; ++jp) {
+    double v = 0.0;
+#pragma unroll
+    for (int ip = 0; ip < Q1; ++ip) v = fma(U[ip], fs[ip * Q1 + jp], v);
+    gby_bar[jp] += v;
+  }
+  // cotangent of the staged populations of this point
+#pragma unroll
+  for (int ip = 0; ip < Q1; ++ip)
+#pragma unroll
+    for (int jp = 0; jp < Q1; ++jp) {
+      const int p = ip * Q1 + jp;
+      const int idx = p < QH ? k + p * WN : kh + (p - QH) * WN;
+      atomicAdd(&s_acc[idx], U[ip] * gby[jp]);
+    }
+}
+
+// Adjoint of a collocation point outside the window (HBM state at (gx, gy),
+// direct transform G_{s->n}): val[i] as above, the cotangent of the pass
+// gauge added to (gux, guy, gs), and the cotangents of the point's own
+// populations and gauge scattered to HBM.
+template <int Q1, class FT, int WX, int WY, int WN>
+__device__ __forceinline__ void adj_hbm_point(const Lane<Q1, FT, WX, WY, WN>& c, const Gauge& G,
+                                              int gx, int gy, const LagRow& Pj, double inv_s,
+                                              const double* cw, double* val, double& gux,
+                                              double& guy, double& gs) {
+  using L = Lat<Q1>;
+  const AdjArgs& A = *c.A;
+  const FT* __restrict__ fin = static_cast<const FT*>(A.f_in);
+  const size_t src = (size_t)wrap_index(gy, A.ny, A.bc_y) * A.nx + wrap_index(gx, A.nx, A.bc_x);
+  double fs[Q1 * Q1];
+#pragma unroll
+  for (int p = 0; p < Q1 * Q1; ++p) fs[p] = double(fin[(size_t)p * c.plane + src]);
+  const double ss = sqrt(A.g_in[2 * c.plane + src] * L::inv_TL);
+  const double r = ss * inv_s;
+  const double dx = (A.g_in[src] - G.ux) * inv_s, dy = (A.g_in[c.plane + src] - G.uy) * inv_s;
+  double zx[Q1], zy[Q1], gyr[Q1];
+#pragma unroll
+  for (int q = 0; q < Q1; ++q) {
+    zx[q] = fma(r, L::c(q), dx);
+    zy[q] = fma(r, L::c(q), dy);
+    gyr[q] = fma(fma(fma(Pj.l3, zy[q], Pj.l2), zy[q], Pj.l1), zy[q], Pj.l0);
+  }
+  double h[Q1], Ux[Q1], dsum[Q1];  // dsum[ip] = sum_i cw_i l_i'(zx[ip])
+#pragma unroll
+  for (int ip = 0; ip < Q1; ++ip) {
+    double v = 0.0;
+#pragma unroll
+    for (int jp = 0; jp < Q1; ++jp) v = fma(gyr[jp], fs[ip * Q1 + jp], v);
+    h[ip] = v;
+    Ux[ip] = 0.0;
+    dsum[ip] = 0.0;
+  }
+#pragma unroll
+  for (int i = 0; i < Q1; ++i) {
+    const LagRow Pi = lag_row<Q1>(i);
+    double v = 0.0;
+#pragma unroll
+    for (int ip = 0; ip < Q1; ++ip) {
+      const double gx_r = fma(fma(fma(Pi.l3, zx[ip], Pi.l2), zx[ip], Pi.l1), zx[ip], Pi.l0);
+      v = fma(gx_r, h[ip], v);
+      Ux[ip] = fma(cw[i], gx_r, Ux[ip]);
+      dsum[ip] = fma(cw[i], lag_deriv(Pi, zx[ip]), dsum[ip]);
+    }
+    val[i] = v;
+  }
+  double zs_x = 0.0, zs_y = 0.0, zsc = 0.0, zz = 0.0;
+#pragma unroll
+  for (int ip = 0; ip < Q1; ++ip) {
+    const double zb = h[ip] * dsum[ip];
+    zs_x += zb;
+    zsc = fma(zb, L::c(ip), zsc);
+    zz = fma(zb, zx[ip], zz);
+  }
+#pragma unroll
+  for (int jp = 0; jp < Q1; ++jp) {
+    double v = 0.0;
+#pragma unroll
+    for (int ip = 0; ip < Q1; ++ip) v = fma(Ux[ip], fs[ip * Q1 + jp], v);
+    const double zb = v * lag_deriv(Pj, zy[jp]);
+    zs_y += zb;
+    zsc = fma(zb, L::c(jp), zsc);
+    zz = fma(zb, zy[jp], zz);
+  }
+  // z = (s_s c + u_s - u) / s
+  gux -= zs_x * inv_s;
+  guy -= zs_y * inv_s;
+  gs -= zz * inv_s;
+  atomicAdd(&A.ag_in[src], zs_x * inv_s);
+  atomicAdd(&A.ag_in[c.plane + src], zs_y * inv_s);
+  // d s_s / d T_s = inv_TL / (2 s_s)
+  atomicAdd(&A.ag_in[2 * c.plane + src], zsc * inv_s * L::inv_TL / (2.0 * ss));
+#pragma unroll
+  for (int ip = 0; ip < Q1; ++ip)
+#pragma unroll
+    for (int jp = 0; jp < Q1; ++jp)
+      atomicAdd(&A.af_in[(size_t)(ip * Q1 + jp) * c.plane + src], Ux[ip] * gyr[jp]);
+}
+
 // Adjoint of one forward pass at gauge G with cotangent Fb of its output.
 // Scatters the collocation points' cotangents and adds the cotangent of the
 // gauge (u_x, u_y, s) to (gux, guy, gs).  Column by column like the forward
@@ -305,8 +477,7 @@ template <int Q1, class FT, int WX, int WY, int WN>
 __device__ void adjoint_pass(const Lane<Q1, FT, WX, WY, WN>& c, const Gauge& G, const double* Fb,
                              double& gux, double& guy, double& gs) {
   using L = Lat<Q1>;
-  const AdjArgs& A = *c.A;
-  const FT* __restrict__ fin = static_cast<const FT*>(A.f_in);
+  constexpr int QH = Q1 * Q1 / 2;
   const double inv_s = 1.0 / G.s;
   const double rB = c.sB * inv_s, dBx = (c.uxB - G.ux) * inv_s, dBy = (c.uyB - G.uy) * inv_s;
   XAxis<Q1> x;
@@ -326,6 +497,8 @@ __device__ void adjoint_pass(const Lane<Q1, FT, WX, WY, WN>& c, const Gauge& G, 
     double ay[4], day[4];
     interp_weights_d(yd - (fly - 1.0), ay, day);
     const int y0 = sat_floor_a(fly) - 1;
+    const int ly0 = y0 - c.wy0;
+    const bool rows_in = (unsigned)ly0 <= (unsigned)(WY - 4);
     const LagRow Pj = lag_row<Q1>(j);
     double gby[Q1], gby_bar[Q1];
     transfer_row_coef<Q1>(Pj, rB, dBy, gby);
@@ -353,132 +526,44 @@ __device__ void adjoint_pass(const Lane<Q1, FT, WX, WY, WN>& c, const Gauge& G, 
         colv[i] = 0.0;
         dcol[i] = 0.0;
       }
+      if (need && rows_in && (unsigned)lx < (unsigned)WX) {
+        const int k = ly0 * WX + lx;
+        int kh = k + QH * WN;
+        asm volatile("" : "+v"(kh));
 #pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        const int gy = y0 + m, ly = gy - c.wy0;
-        const double aym = pick4(ay, m), daym = pick4(day, m);  // constant index once unrolled
-        double cw[Q1], val[Q1];
+        for (int m = 0; m < 4; ++m) {
+          const double aym = pick4(ay, m), daym = pick4(day, m);  // constant index once unrolled
+          double cw[Q1], val[Q1];
 #pragma unroll
-        for (int i = 0; i < Q1; ++i) {
-          cw[i] = fb[i] * wx[i] * aym;
-          val[i] = 0.0;
+          for (int i = 0; i < Q1; ++i) cw[i] = fb[i] * wx[i] * aym;
+          adj_window_point<Q1, WN>(c.s_fB, c.s_acc, k + m * WX, kh + m * WX, gby, x.gbx, cw, val,
+                                   gbx_bar, gby_bar);
+#pragma unroll
+          for (int i = 0; i < Q1; ++i) {
+            colv[i] = fma(aym, val[i], colv[i]);
+            dcol[i] = fma(daym, val[i], dcol[i]);
+          }
         }
-        if (need && (unsigned)lx < (unsigned)WX && (unsigned)ly < (unsigned)WY) {
-          const int k = ly * WX + lx;
-          double fs[Q1 * Q1];
+      } else if (need) {
+#pragma unroll 1
+        for (int m = 0; m < 4; ++m) {
+          const int gy = y0 + m, ly = gy - c.wy0;
+          const double aym = pick4(ay, m), daym = pick4(day, m);
+          double cw[Q1], val[Q1];
 #pragma unroll
-          for (int p = 0; p < Q1 * Q1; ++p) fs[p] = c.s_fB[p * WN + k];
-          double h[Q1], U[Q1];
-#pragma unroll
-          for (int ip = 0; ip < Q1; ++ip) {
-            double v = 0.0;
-#pragma unroll
-            for (int jp = 0; jp < Q1; ++jp) v = fma(gby[jp], fs[ip * Q1 + jp], v);
-            h[ip] = v;
-            double u = 0.0;
-#pragma unroll
-            for (int i = 0; i < Q1; ++i) u = fma(cw[i], x.gbx[i][ip], u);
-            U[ip] = u;
+          for (int i = 0; i < Q1; ++i) cw[i] = fb[i] * wx[i] * aym;
+          if ((unsigned)lx < (unsigned)WX && (unsigned)ly < (unsigned)WY) {
+            const int kk = ly * WX + lx;
+            adj_window_point<Q1, WN>(c.s_fB, c.s_acc, kk, kk + QH * WN, gby, x.gbx, cw, val,
+                                     gbx_bar, gby_bar);
+          } else {
+            adj_hbm_point<Q1, FT, WX, WY, WN>(c, G, gx, gy, Pj, inv_s, cw, val, gux, guy, gs);
           }
 #pragma unroll
           for (int i = 0; i < Q1; ++i) {
-            double v = 0.0;
-#pragma unroll
-            for (int ip = 0; ip < Q1; ++ip) {
-              v = fma(x.gbx[i][ip], h[ip], v);
-              gbx_bar[i][ip] = fma(cw[i], h[ip], gbx_bar[i][ip]);
-            }
-            val[i] = v;
+            colv[i] = fma(aym, val[i], colv[i]);
+            dcol[i] = fma(daym, val[i], dcol[i]);
           }
-#pragma unroll
-          for (int jp = 0; jp < Q1; ++jp) {
-            double v = 0.0;
-#pragma unroll
-            for (int ip = 0; ip < Q1; ++ip) v = fma(U[ip], fs[ip * Q1 + jp], v);
-            gby_bar[jp] += v;
-          }
-          // cotangent of the staged populations of this point
-#pragma unroll
-          for (int ip = 0; ip < Q1; ++ip)
-#pragma unroll
-            for (int jp = 0; jp < Q1; ++jp)
-              atomicAdd(&c.s_acc[(ip * Q1 + jp) * WN + k], U[ip] * gby[jp]);
-        } else if (need) {
-          // direct transform G_{s->n}; scatter to HBM, source gauge included
-          const size_t src =
-              (size_t)wrap_index(gy, A.ny, A.bc_y) * A.nx + wrap_index(gx, A.nx, A.bc_x);
-          double fs[Q1 * Q1];
-#pragma unroll
-          for (int p = 0; p < Q1 * Q1; ++p) fs[p] = double(fin[(size_t)p * c.plane + src]);
-          const double ss = sqrt(A.g_in[2 * c.plane + src] * L::inv_TL);
-          const double r = ss * inv_s;
-          const double dx = (A.g_in[src] - G.ux) * inv_s, dy = (A.g_in[c.plane + src] - G.uy) * inv_s;
-          double zx[Q1], zy[Q1], gyr[Q1];
-#pragma unroll
-          for (int q = 0; q < Q1; ++q) {
-            zx[q] = fma(r, L::c(q), dx);
-            zy[q] = fma(r, L::c(q), dy);
-            gyr[q] = fma(fma(fma(Pj.l3, zy[q], Pj.l2), zy[q], Pj.l1), zy[q], Pj.l0);
-          }
-          double h[Q1], Ux[Q1], dsum[Q1];  // dsum[ip] = sum_i cw_i l_i'(zx[ip])
-#pragma unroll
-          for (int ip = 0; ip < Q1; ++ip) {
-            double v = 0.0;
-#pragma unroll
-            for (int jp = 0; jp < Q1; ++jp) v = fma(gyr[jp], fs[ip * Q1 + jp], v);
-            h[ip] = v;
-            Ux[ip] = 0.0;
-            dsum[ip] = 0.0;
-          }
-#pragma unroll
-          for (int i = 0; i < Q1; ++i) {
-            const LagRow Pi = lag_row<Q1>(i);
-            double v = 0.0;
-#pragma unroll
-            for (int ip = 0; ip < Q1; ++ip) {
-              const double gx_r = fma(fma(fma(Pi.l3, zx[ip], Pi.l2), zx[ip], Pi.l1), zx[ip], Pi.l0);
-              v = fma(gx_r, h[ip], v);
-              Ux[ip] = fma(cw[i], gx_r, Ux[ip]);
-              dsum[ip] = fma(cw[i], lag_deriv(Pi, zx[ip]), dsum[ip]);
-            }
-            val[i] = v;
-          }
-          double zs_x = 0.0, zs_y = 0.0, zsc = 0.0, zz = 0.0;
-#pragma unroll
-          for (int ip = 0; ip < Q1; ++ip) {
-            const double zb = h[ip] * dsum[ip];
-            zs_x += zb;
-            zsc = fma(zb, L::c(ip), zsc);
-            zz = fma(zb, zx[ip], zz);
-          }
-#pragma unroll
-          for (int jp = 0; jp < Q1; ++jp) {
-            double v = 0.0;
-#pragma unroll
-            for (int ip = 0; ip < Q1; ++ip) v = fma(Ux[ip], fs[ip * Q1 + jp], v);
-            const double zb = v * lag_deriv(Pj, zy[jp]);
-            zs_y += zb;
-            zsc = fma(zb, L::c(jp), zsc);
-            zz = fma(zb, zy[jp], zz);
-          }
-          // z = (s_s c + u_s - u) / s
-          gux -= zs_x * inv_s;
-          guy -= zs_y * inv_s;
-          gs -= zz * inv_s;
-          atomicAdd(&A.ag_in[src], zs_x * inv_s);
-          atomicAdd(&A.ag_in[c.plane + src], zs_y * inv_s);
-          // d s_s / d T_s = inv_TL / (2 s_s)
-          atomicAdd(&A.ag_in[2 * c.plane + src], zsc * inv_s * L::inv_TL / (2.0 * ss));
-#pragma unroll
-          for (int ip = 0; ip < Q1; ++ip)
-#pragma unroll
-            for (int jp = 0; jp < Q1; ++jp)
-              atomicAdd(&A.af_in[(size_t)(ip * Q1 + jp) * c.plane + src], Ux[ip] * gyr[jp]);
-        }
-#pragma unroll
-        for (int i = 0; i < Q1; ++i) {
-          colv[i] = fma(aym, val[i], colv[i]);
-          dcol[i] = fma(daym, val[i], dcol[i]);
         }
       }
 #pragma unroll
