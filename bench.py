@@ -31,11 +31,14 @@ if ROOT not in sys.path:
 
 from paper_1806_05089_amd import autograd, pond, workloads  # noqa: E402
 
-# Algorithmic flop count per node and predictor-corrector pass: 16 populations
-# x 16 collocation points x (42 flops for the row-Kronecker contraction and
-# weighted accumulate + 64 flops for the two transfer rows built per pair in
-# the direct form); per node and step, 560 flops for the regauge and BGK.
-FLOPS_PER_NODE_PASS = 16 * 16 * 42 + 16 * 16 * 64
+# Algorithmic flop count per node and predictor-corrector pass, the floor the
+# method needs whatever the kernel: 16 populations x 16 collocation points x
+# 42 flops (row-Kronecker contraction of a transformed point, 2(q^2 + q), and
+# its weighted accumulate, 2), 8 departure coordinates x 16 flops for the
+# Lagrange weights, 7 x 16 flops for the four moments.  Transfer-row
+# construction is not counted (it depends on how rows are shared).  Per node
+# and step, 560 flops for the regauge and BGK.
+FLOPS_PER_NODE_PASS = 16 * 16 * 42 + 8 * 16 + 7 * 16
 FLOPS_PER_NODE_STEP = 560
 PEAK_FP64_TFLOPS = 78.6   # MI355X vector FP64: 256 CU x 2.4 GHz x 64 lanes x 2
 PEAK_FP32_TFLOPS = 157.3  # MI355X published FP32 peak

@@ -170,6 +170,18 @@ __device__ __forceinline__ double speed_rt(int i) {
 // ----------------------------------------------- reconstruction (App. C)
 // Third-order Lagrange weights on the four collocation points x0 + n,
 // x0 = floor(x) - 1, at local coordinate t = x - x0 in [1, 2).
+// Weight of column n of a stencil, zero for n outside 0..3: the same products
+// as interp_weight_at, the constant factor zeroed outside.  The factor is a
+// sign and a magnitude picked by two-way selects (a four-way chain on n is
+// compiled into branches).
+__device__ __forceinline__ double interp_weight_masked(int n, double t) {
+  const double e1 = t - (n == 0 ? 1.0 : 0.0);
+  const double e2 = t - (n <= 1 ? 2.0 : 1.0);
+  const double e3 = t - (n <= 2 ? 3.0 : 2.0);
+  const double mag = ((n + 1) & 2) == 0 ? 1.0 / 6.0 : 0.5;  // nodes 0, 3 : 1, 2
+  const double cn = (n & 1) ? mag : -mag;
+  return e1 * e2 * e3 * ((unsigned)n < 4u ? cn : 0.0);
+}
 __device__ __forceinline__ void interp_weights(double t, double* a) {
   const double t0 = t, t1 = t - 1.0, t2 = t - 2.0, t3 = t - 3.0;
   a[0] = t1 * t2 * t3 * (-1.0 / 6.0);

@@ -711,7 +711,12 @@ k_step(StepArgs A) {
             for (int i = 0; i < Q1; ++i) {
               const int n = rel - o[i];
               const bool in = (unsigned)n < 4u;
-              wx[i] = in ? FT(interp_weight_at(n, tx[i])) : FT(0);
+              // FP64: a wave skips the weight of a speed none of its lanes
+              // needs (measured faster); FP32: branch-free
+              if constexpr (sizeof(FT) == 8)
+                wx[i] = in ? FT(interp_weight_at(n, tx[i])) : FT(0);
+              else
+                wx[i] = FT(interp_weight_masked(n, tx[i]));
               need = need || in;
             }
             if (!__any(need)) continue;
