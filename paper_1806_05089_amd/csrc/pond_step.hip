@@ -33,6 +33,37 @@ constexpr int kWaveTX = 32;
 namespace pond {
 namespace {
 
+// LDS layout of the staged window: the Q values of a window node are kept in
+// groups of G = 16 / sizeof(FT) populations whose values are adjacent, so
+// that a group is one 16-byte LDS read.  Group g of node k starts at element
+// g * G * WN + k * G.
+template <int Q1, class FT, int WN>
+struct Win {
+  static constexpr int Q = Q1 * Q1;
+  static constexpr int G = 16 / (int)sizeof(FT);
+  static constexpr int NG = (Q + G - 1) / G;
+  static constexpr int NGH = NG / 2;  // groups read from the first base
+  static constexpr int GS = G * WN;   // group stride in elements
+  static constexpr int size = NG * GS;
+  using V = FT __attribute__((ext_vector_type(16 / sizeof(FT))));
+  __device__ static int at(int p, int k) { return (p / G) * GS + k * G + p % G; }
+  // The Q values of a node, element offset e = k * G; groups from NGH on are
+  // read from eh = e + NGH * GS (a second base keeps every offset within the
+  // 16-bit offset field of the read).
+  __device__ static void load(const FT* s, int e, int eh, FT* f) {
+    V v[NG];
+#pragma unroll
+    for (int g = 0; g < NGH; ++g) v[g] = *reinterpret_cast<const V*>(s + e + g * GS);
+#pragma unroll
+    for (int g = NGH; g < NG; ++g) v[g] = *reinterpret_cast<const V*>(s + eh + (g - NGH) * GS);
+#pragma unroll
+    for (int g = 0; g < NG; ++g)
+#pragma unroll
+      for (int c = 0; c < G; ++c)
+        if (g * G + c < Q) f[g * G + c] = v[g][c];
+  }
+};
+
 template <int Q1, class FT, int TX, int TY, int H>
 struct TileShape {
   static constexpr int WX = TX + 2 * H;
@@ -40,7 +71,7 @@ struct TileShape {
   static constexpr int WN = WX * WY;
   static constexpr int NT = TX * TY;
   static constexpr int NW = NT / 64;
-  static constexpr size_t lds_bytes = (size_t)Q1 * Q1 * WN * sizeof(FT);
+  static constexpr size_t lds_bytes = (size_t)Win<Q1, FT, WN>::size * sizeof(FT);
   static constexpr int WTX = kWaveTX;
   static constexpr int WTY = 64 / WTX;  // wave tile
   static_assert(TX % WTX == 0 && TY % WTY == 0, "waves tile the block");
@@ -159,10 +190,10 @@ __device__ __forceinline__ FT pair_value(const StepArgs& A, const FT* s_f, int w
   const int lx = gx - wx0, ly = gy - wy0;
   FT t = FT(0);
   if ((unsigned)lx < (unsigned)WX && (unsigned)ly < (unsigned)WY) {
+    using W = Win<Q1, FT, WN>;
     const int k = ly * WX + lx;
     FT f[Q1 * Q1];
-#pragma unroll
-    for (int p = 0; p < Q1 * Q1; ++p) f[p] = s_f[p * WN + k];
+    W::load(s_f, k * W::G, k * W::G + W::NGH * W::GS, f);
 #pragma unroll
     for (int ip = 0; ip < Q1; ++ip) {
       FT h = FT(0);
@@ -191,11 +222,11 @@ __device__ __forceinline__ void column_point(const StepArgs& A, const FT* s_f, i
   using L = Lat<Q1>;
   const int lx = gx - wx0, ly = gy - wy0;
   if (need && (unsigned)lx < (unsigned)WX && (unsigned)ly < (unsigned)WY) {
+    using W = Win<Q1, FT, WN>;
     const int k = ly * WX + lx;
-    // all Q loads first, so that they are in flight together
+    // all loads first, so that they are in flight together
     FT f[Q1 * Q1];
-#pragma unroll
-    for (int p = 0; p < Q1 * Q1; ++p) f[p] = s_f[p * WN + k];
+    W::load(s_f, k * W::G, k * W::G + W::NGH * W::GS, f);
 #pragma unroll
     for (int ip = 0; ip < Q1; ++ip) {
       FT v = FT(0);
@@ -235,26 +266,25 @@ __device__ __forceinline__ void column_point(const StepArgs& A, const FT* s_f, i
 }
 
 // a4 + a5 on the LDS window for the four rows of one stencil column, the
-// lane's whole column inside the window (index k of its first row): the y
-// contractions with the G_{B->n} row gby, weighted by ayw and summed into hc.
-// The planes are addressed from two bases (planes below and above Q/2) so
-// that every load takes its plane and row from the 16-bit instruction offset.
-// In FP64 each row's loads are kept with their row: left free, the scheduler
-// pairs the rows into ds_read2_b64 and holds all 4 x Q values of the column
-// at once, which measured slower; FP32 gains from the pairing.
+// lane's whole column inside the window (node index k of its first row): the
+// y contractions with the G_{B->n} row gby, weighted by ayw and summed into
+// hc.  The second base of the reads is opaque to the optimiser, so that every
+// read takes its group and row from the instruction offset.  In FP64 each
+// row's reads are kept with their row: left free, the scheduler hoists the
+// reads of all four rows and holds them at once, which measured slower; FP32
+// gains from it.
 template <int Q1, class FT, int WX, int WN>
 __device__ __forceinline__ void window_column(const FT* s_f, int k, const FT* ayw, const FT* gby,
                                               FT* hc) {
-  constexpr int Q = Q1 * Q1, QH = Q / 2;
-  int kh = k + QH * WN;
-  asm volatile("" : "+v"(kh));
+  using W = Win<Q1, FT, WN>;
+  constexpr int Q = Q1 * Q1;
+  const int e = k * W::G;
+  int eh = e + W::NGH * W::GS;
+  asm volatile("" : "+v"(eh));
 #pragma unroll
   for (int m = 0; m < 4; ++m) {
     FT f[Q];
-#pragma unroll
-    for (int p = 0; p < QH; ++p) f[p] = s_f[k + p * WN + m * WX];
-#pragma unroll
-    for (int p = QH; p < Q; ++p) f[p] = s_f[kh + (p - QH) * WN + m * WX];
+    W::load(s_f, e + m * WX * W::G, eh + m * WX * W::G, f);
 #pragma unroll
     for (int ip = 0; ip < Q1; ++ip) {
       FT v = FT(0);
@@ -489,7 +519,7 @@ k_step(StepArgs A) {
   using L = Lat<Q1>;
   using TS = TileShape<Q1, FT, TX, TY, H>;
   constexpr int WX = TS::WX, WY = TS::WY, WN = TS::WN, NT = TS::NT;
-  __shared__ FT s_f[Q * WN];
+  __shared__ __align__(16) FT s_f[Win<Q1, FT, WN>::size];
   __shared__ int s_ri[4 * TS::NW];
   __shared__ double s_rd[4 * TS::NW];
   __shared__ unsigned s_list[NT];  // deferred nodes: local index | passes << 16
@@ -619,7 +649,7 @@ k_step(StepArgs A) {
             double t = 0.0;
 #pragma unroll
             for (int i = 0; i < Q1; ++i) t = fma(Gx[kk * Q1 + i], Hm[i * Q1 + l], t);
-            s_f[(kk * Q1 + l) * WN + k] = FT(t);
+            s_f[Win<Q1, FT, WN>::at(kk * Q1 + l, k)] = FT(t);
           }
       }
     }
