@@ -642,6 +642,8 @@ k_step(StepArgs A) {
             for (int j = 0; j < Q1; ++j) h = fma(Gy[l * Q1 + j], f[i * Q1 + j], h);
             Hm[i * Q1 + l] = h;
           }
+        using W = Win<Q1, FT, WN>;
+        typename W::V tv[W::NG];  // one 16-byte LDS write per group
 #pragma unroll
         for (int kk = 0; kk < Q1; ++kk)
 #pragma unroll
@@ -649,8 +651,19 @@ k_step(StepArgs A) {
             double t = 0.0;
 #pragma unroll
             for (int i = 0; i < Q1; ++i) t = fma(Gx[kk * Q1 + i], Hm[i * Q1 + l], t);
-            s_f[Win<Q1, FT, WN>::at(kk * Q1 + l, k)] = FT(t);
+            const int p = kk * Q1 + l;
+            tv[p / W::G][p % W::G] = FT(t);
           }
+#pragma unroll
+        for (int g = 0; g < W::NG; ++g) {
+          if constexpr (W::NG * W::G > Q) {  // padding of the last group
+            if (g == W::NG - 1) {
+#pragma unroll
+              for (int c = Q % W::G; c < W::G; ++c) tv[g][c] = FT(0);
+            }
+          }
+          *reinterpret_cast<typename W::V*>(s_f + g * W::GS + k * W::G) = tv[g];
+        }
       }
     }
     __syncthreads();
