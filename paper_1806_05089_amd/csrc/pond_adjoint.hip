@@ -96,7 +96,9 @@ struct AdjShape {
   static constexpr int WN = WX * WY;
   static constexpr int NT = TX * TY;
   static constexpr int NW = NT / 64;
-  static_assert(2 * (size_t)Q1 * Q1 * WN * sizeof(double) + 1024 <= 160 * 1024, "LDS");
+  static_assert(((size_t)Win<Q1, double, WN>::size + (size_t)Q1 * Q1 * WN) * sizeof(double) + 1024 <=
+                    160 * 1024,
+                "LDS");
 };
 
 // Context of one lane: everything the per-pass routines need.
@@ -197,18 +199,15 @@ __device__ __forceinline__ double pick4(const double* a, int m) {
   return m == 0 ? a[0] : m == 1 ? a[1] : m == 2 ? a[2] : a[3];
 }
 
-// Window part of a forward collocation point (LDS index k; planes below Q/2
-// from k, the others from kh = k + Q/2 WN): the y contraction with the
+// Window part of a forward collocation point (staged values at element
+// offsets e, eh of the grouped window layout): the y contraction with the
 // G_{B->n} row gby, weighted by aym and added to hc.
 template <int Q1, int WN>
-__device__ __forceinline__ void fwd_window_point(const double* s_fB, int k, int kh, double aym,
+__device__ __forceinline__ void fwd_window_point(const double* s_fB, int e, int eh, double aym,
                                                  const double* gby, double* hc) {
-  constexpr int Q = Q1 * Q1, QH = Q / 2;
+  constexpr int Q = Q1 * Q1;
   double fs[Q];  // all loads first, so that they are in flight together
-#pragma unroll
-  for (int p = 0; p < QH; ++p) fs[p] = s_fB[k + p * WN];
-#pragma unroll
-  for (int p = QH; p < Q; ++p) fs[p] = s_fB[kh + (p - QH) * WN];
+  Win<Q1, double, WN>::load(s_fB, e, eh, fs);
 #pragma unroll
   for (int ip = 0; ip < Q1; ++ip) {
     double v = 0.0;
@@ -261,7 +260,7 @@ __device__ __forceinline__ void fwd_hbm_point(const Lane<Q1, FT, WX, WY, WN>& c,
 // otherwise point by point, from LDS or HBM.
 template <int Q1, class FT, int WX, int WY, int WN>
 __device__ void forward_pass(const Lane<Q1, FT, WX, WY, WN>& c, const Gauge& G, double* F) {
-  constexpr int QH = Q1 * Q1 / 2;
+  using W = Win<Q1, double, WN>;
   const double inv_s = 1.0 / G.s;
   const double rB = c.sB * inv_s, dBx = (c.uxB - G.ux) * inv_s, dBy = (c.uyB - G.uy) * inv_s;
   XAxis<Q1> x;
@@ -294,20 +293,21 @@ __device__ void forward_pass(const Lane<Q1, FT, WX, WY, WN>& c, const Gauge& G, 
 #pragma unroll
       for (int ip = 0; ip < Q1; ++ip) hc[ip] = 0.0;
       if (need && rows_in && (unsigned)lx < (unsigned)WX) {
-        const int k = ly0 * WX + lx;
-        int kh = k + QH * WN;
-        asm volatile("" : "+v"(kh));
+        const int e = (ly0 * WX + lx) * W::G;
+        int eh = e + W::NGH * W::GS;
+        asm volatile("" : "+v"(eh));
 #pragma unroll
         for (int m = 0; m < 4; ++m)
-          fwd_window_point<Q1, WN>(c.s_fB, k + m * WX, kh + m * WX, pick4(ay, m), gby, hc);
+          fwd_window_point<Q1, WN>(c.s_fB, e + m * WX * W::G, eh + m * WX * W::G, pick4(ay, m),
+                                   gby, hc);
       } else if (need) {
 #pragma unroll 1
         for (int m = 0; m < 4; ++m) {
           const int gy = y0 + m, ly = gy - c.wy0;
           const double aym = pick4(ay, m);
           if ((unsigned)lx < (unsigned)WX && (unsigned)ly < (unsigned)WY) {
-            const int k = ly * WX + lx;
-            fwd_window_point<Q1, WN>(c.s_fB, k, k + QH * WN, aym, gby, hc);
+            const int e = (ly * WX + lx) * W::G;
+            fwd_window_point<Q1, WN>(c.s_fB, e, e + W::NGH * W::GS, aym, gby, hc);
           } else {
             fwd_hbm_point<Q1, FT, WX, WY, WN>(c, G, gx, gy, aym, wx, Pj, inv_s, acc);
           }
@@ -329,23 +329,22 @@ __device__ void forward_pass(const Lane<Q1, FT, WX, WY, WN>& c, const Gauge& G, 
   }
 }
 
-// Adjoint of a window collocation point (LDS index k; planes below Q/2 from
-// k, the others from kh = k + Q/2 WN) for one row: val[i] = x speed i's
+// Adjoint of a window collocation point for one row (staged values at
+// element offsets e, eh of the grouped window layout; cotangent planes below
+// Q/2 from index k, the others from kh = k + Q/2 WN): val[i] = x speed i's
 // transformed value (before weights), cotangents of the G_{B->n} rows
 // accumulated in gbx_bar / gby_bar, and the cotangent of the staged
 // populations scattered into the LDS accumulators.  cw[i] is the cotangent
 // of the point's contribution to x speed i.
 template <int Q1, int WN>
-__device__ __forceinline__ void adj_window_point(const double* s_fB, double* s_acc, int k, int kh,
-                                                 const double* gby, const double (*gbx)[Q1],
-                                                 const double* cw, double* val,
-                                                 double (*gbx_bar)[Q1], double* gby_bar) {
+__device__ __forceinline__ void adj_window_point(const double* s_fB, double* s_acc, int e, int eh,
+                                                 int k, int kh, const double* gby,
+                                                 const double (*gbx)[Q1], const double* cw,
+                                                 double* val, double (*gbx_bar)[Q1],
+                                                 double* gby_bar) {
   constexpr int Q = Q1 * Q1, QH = Q / 2;
   double fs[Q];
-#pragma unroll
-  for (int p = 0; p < QH; ++p) fs[p] = s_fB[k + p * WN];
-#pragma unroll
-  for (int p = QH; p < Q; ++p) fs[p] = s_fB[kh + (p - QH) * WN];
+  Win<Q1, double, WN>::load(s_fB, e, eh, fs);
   double h[Q1], U[Q1];
 #pragma unroll
   for (int ip = 0; ip < Q1; ++ip) {
@@ -477,6 +476,7 @@ template <int Q1, class FT, int WX, int WY, int WN>
 __device__ void adjoint_pass(const Lane<Q1, FT, WX, WY, WN>& c, const Gauge& G, const double* Fb,
                              double& gux, double& guy, double& gs) {
   using L = Lat<Q1>;
+  using W = Win<Q1, double, WN>;
   constexpr int QH = Q1 * Q1 / 2;
   const double inv_s = 1.0 / G.s;
   const double rB = c.sB * inv_s, dBx = (c.uxB - G.ux) * inv_s, dBy = (c.uyB - G.uy) * inv_s;
@@ -530,14 +530,17 @@ __device__ void adjoint_pass(const Lane<Q1, FT, WX, WY, WN>& c, const Gauge& G, 
         const int k = ly0 * WX + lx;
         int kh = k + QH * WN;
         asm volatile("" : "+v"(kh));
+        const int e = k * W::G;
+        int eh = e + W::NGH * W::GS;
+        asm volatile("" : "+v"(eh));
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
           const double aym = pick4(ay, m), daym = pick4(day, m);  // constant index once unrolled
           double cw[Q1], val[Q1];
 #pragma unroll
           for (int i = 0; i < Q1; ++i) cw[i] = fb[i] * wx[i] * aym;
-          adj_window_point<Q1, WN>(c.s_fB, c.s_acc, k + m * WX, kh + m * WX, gby, x.gbx, cw, val,
-                                   gbx_bar, gby_bar);
+          adj_window_point<Q1, WN>(c.s_fB, c.s_acc, e + m * WX * W::G, eh + m * WX * W::G,
+                                   k + m * WX, kh + m * WX, gby, x.gbx, cw, val, gbx_bar, gby_bar);
 #pragma unroll
           for (int i = 0; i < Q1; ++i) {
             colv[i] = fma(aym, val[i], colv[i]);
@@ -554,8 +557,8 @@ __device__ void adjoint_pass(const Lane<Q1, FT, WX, WY, WN>& c, const Gauge& G, 
           for (int i = 0; i < Q1; ++i) cw[i] = fb[i] * wx[i] * aym;
           if ((unsigned)lx < (unsigned)WX && (unsigned)ly < (unsigned)WY) {
             const int kk = ly * WX + lx;
-            adj_window_point<Q1, WN>(c.s_fB, c.s_acc, kk, kk + QH * WN, gby, x.gbx, cw, val,
-                                     gbx_bar, gby_bar);
+            adj_window_point<Q1, WN>(c.s_fB, c.s_acc, kk * W::G, kk * W::G + W::NGH * W::GS, kk,
+                                     kk + QH * WN, gby, x.gbx, cw, val, gbx_bar, gby_bar);
           } else {
             adj_hbm_point<Q1, FT, WX, WY, WN>(c, G, gx, gy, Pj, inv_s, cw, val, gux, guy, gs);
           }
@@ -613,7 +616,7 @@ k_step_adjoint(AdjArgs A) {
   using L = Lat<Q1>;
   using S = AdjShape<Q1, FT, TX, TY, H>;
   constexpr int WX = S::WX, WY = S::WY, WN = S::WN, NT = S::NT;
-  __shared__ double s_fB[Q * WN];
+  __shared__ __align__(16) double s_fB[Win<Q1, double, WN>::size];
   __shared__ double s_acc[Q * WN];
   __shared__ int s_ri[4 * S::NW];
   __shared__ double s_rd[4 * S::NW];
@@ -732,7 +735,7 @@ k_step_adjoint(AdjArgs A) {
             for (int j = 0; j < Q1; ++j) h = fma(Gy[l * Q1 + j], f[i * Q1 + j], h);
             t = fma(Gx[kk * Q1 + i], h, t);
           }
-          s_fB[(kk * Q1 + l) * WN + k] = t;
+          s_fB[Win<Q1, double, WN>::at(kk * Q1 + l, k)] = t;
           s_acc[(kk * Q1 + l) * WN + k] = 0.0;
         }
     }

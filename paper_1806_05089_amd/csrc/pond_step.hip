@@ -33,37 +33,6 @@ constexpr int kWaveTX = 32;
 namespace pond {
 namespace {
 
-// LDS layout of the staged window: the Q values of a window node are kept in
-// groups of G = 16 / sizeof(FT) populations whose values are adjacent, so
-// that a group is one 16-byte LDS read.  Group g of node k starts at element
-// g * G * WN + k * G.
-template <int Q1, class FT, int WN>
-struct Win {
-  static constexpr int Q = Q1 * Q1;
-  static constexpr int G = 16 / (int)sizeof(FT);
-  static constexpr int NG = (Q + G - 1) / G;
-  static constexpr int NGH = NG / 2;  // groups read from the first base
-  static constexpr int GS = G * WN;   // group stride in elements
-  static constexpr int size = NG * GS;
-  using V = FT __attribute__((ext_vector_type(16 / sizeof(FT))));
-  __device__ static int at(int p, int k) { return (p / G) * GS + k * G + p % G; }
-  // The Q values of a node, element offset e = k * G; groups from NGH on are
-  // read from eh = e + NGH * GS (a second base keeps every offset within the
-  // 16-bit offset field of the read).
-  __device__ static void load(const FT* s, int e, int eh, FT* f) {
-    V v[NG];
-#pragma unroll
-    for (int g = 0; g < NGH; ++g) v[g] = *reinterpret_cast<const V*>(s + e + g * GS);
-#pragma unroll
-    for (int g = NGH; g < NG; ++g) v[g] = *reinterpret_cast<const V*>(s + eh + (g - NGH) * GS);
-#pragma unroll
-    for (int g = 0; g < NG; ++g)
-#pragma unroll
-      for (int c = 0; c < G; ++c)
-        if (g * G + c < Q) f[g * G + c] = v[g][c];
-  }
-};
-
 template <int Q1, class FT, int TX, int TY, int H>
 struct TileShape {
   static constexpr int WX = TX + 2 * H;
