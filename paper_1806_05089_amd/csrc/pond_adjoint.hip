@@ -385,6 +385,82 @@ __device__ __forceinline__ void adj_window_point(const double* s_fB, double* s_a
     }
 }
 
+// Adjoint of the four window rows of a column in one run (the lane's whole
+// column inside the window; staged values at element offsets e, eh, the
+// cotangent planes at indices k, kh, of the first row).  The cotangent of a
+// row's transformed point is its y weight times the vector Uc, fixed per
+// column, and the x rows of G_{B->n} act on sums over the rows (hc, hd with
+// the weights and their derivatives), so a row costs its y contraction, the
+// cotangent of the y row and its scatter.  colv / dcol get the column's
+// values of the x speeds weighted with ay / day.
+template <int Q1, int WX, int WN>
+__device__ __forceinline__ void adj_window_column(const double* s_fB, double* s_acc, int e, int eh,
+                                                  int k, int kh, const double* ay,
+                                                  const double* day, const double* fb,
+                                                  const double* wx, const double* gby,
+                                                  const double (*gbx)[Q1], double* colv,
+                                                  double* dcol, double (*gbx_bar)[Q1],
+                                                  double* gby_bar) {
+  using W = Win<Q1, double, WN>;
+  constexpr int Q = Q1 * Q1, QH = Q / 2;
+  double fw[Q1], Uc[Q1], hc[Q1], hd[Q1];
+#pragma unroll
+  for (int i = 0; i < Q1; ++i) fw[i] = fb[i] * wx[i];
+#pragma unroll
+  for (int ip = 0; ip < Q1; ++ip) {
+    double u = 0.0;
+#pragma unroll
+    for (int i = 0; i < Q1; ++i) u = fma(fw[i], gbx[i][ip], u);
+    Uc[ip] = u;
+    hc[ip] = 0.0;
+    hd[ip] = 0.0;
+  }
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    const double aym = pick4(ay, m), daym = pick4(day, m);  // constant index once unrolled
+    double fs[Q];
+    W::load(s_fB, e + m * WX * W::G, eh + m * WX * W::G, fs);
+    double U[Q1];
+#pragma unroll
+    for (int ip = 0; ip < Q1; ++ip) {
+      double v = 0.0;
+#pragma unroll
+      for (int jp = 0; jp < Q1; ++jp) v = fma(gby[jp], fs[ip * Q1 + jp], v);
+      hc[ip] = fma(aym, v, hc[ip]);
+      hd[ip] = fma(daym, v, hd[ip]);
+      U[ip] = aym * Uc[ip];
+    }
+#pragma unroll
+    for (int jp = 0; jp < Q1; ++jp) {
+      double v = 0.0;
+#pragma unroll
+      for (int ip = 0; ip < Q1; ++ip) v = fma(U[ip], fs[ip * Q1 + jp], v);
+      gby_bar[jp] += v;
+    }
+    // cotangent of the staged populations of this point
+#pragma unroll
+    for (int ip = 0; ip < Q1; ++ip)
+#pragma unroll
+      for (int jp = 0; jp < Q1; ++jp) {
+        const int p = ip * Q1 + jp;
+        const int idx = (p < QH ? k + p * WN : kh + (p - QH) * WN) + m * WX;
+        atomicAdd(&s_acc[idx], U[ip] * gby[jp]);
+      }
+  }
+#pragma unroll
+  for (int i = 0; i < Q1; ++i) {
+    double v = 0.0, d = 0.0;
+#pragma unroll
+    for (int ip = 0; ip < Q1; ++ip) {
+      v = fma(gbx[i][ip], hc[ip], v);
+      d = fma(gbx[i][ip], hd[ip], d);
+      gbx_bar[i][ip] = fma(fw[i], hc[ip], gbx_bar[i][ip]);
+    }
+    colv[i] = v;
+    dcol[i] = d;
+  }
+}
+
 // Adjoint of a collocation point outside the window (HBM state at (gx, gy),
 // direct transform G_{s->n}): val[i] as above, the cotangent of the pass
 // gauge added to (gux, guy, gs), and the cotangents of the point's own
@@ -533,20 +609,8 @@ __device__ void adjoint_pass(const Lane<Q1, FT, WX, WY, WN>& c, const Gauge& G, 
         const int e = k * W::G;
         int eh = e + W::NGH * W::GS;
         asm volatile("" : "+v"(eh));
-#pragma unroll
-        for (int m = 0; m < 4; ++m) {
-          const double aym = pick4(ay, m), daym = pick4(day, m);  // constant index once unrolled
-          double cw[Q1], val[Q1];
-#pragma unroll
-          for (int i = 0; i < Q1; ++i) cw[i] = fb[i] * wx[i] * aym;
-          adj_window_point<Q1, WN>(c.s_fB, c.s_acc, e + m * WX * W::G, eh + m * WX * W::G,
-                                   k + m * WX, kh + m * WX, gby, x.gbx, cw, val, gbx_bar, gby_bar);
-#pragma unroll
-          for (int i = 0; i < Q1; ++i) {
-            colv[i] = fma(aym, val[i], colv[i]);
-            dcol[i] = fma(daym, val[i], dcol[i]);
-          }
-        }
+        adj_window_column<Q1, WX, WN>(c.s_fB, c.s_acc, e, eh, k, kh, ay, day, fb, wx, gby, x.gbx,
+                                      colv, dcol, gbx_bar, gby_bar);
       } else if (need) {
 #pragma unroll 1
         for (int m = 0; m < 4; ++m) {
