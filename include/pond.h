@@ -30,8 +30,11 @@
  *     synchronisation when a larger grid appears); it is held until the
  *     process ends.  A step leaves its tiles' costs there, and the next step
  *     on the same stream takes the costliest tiles first; results do not
- *     depend on that order.  Calls on one stream run in order; concurrent
- *     calls on different streams use different slots.
+ *     depend on that order.  pond_step_adjoint also keeps its scratch there:
+ *     ((K + 1) * 4 + q1d^2) * nx * ny doubles of pass history (K = fixed_iter,
+ *     or max_iter in adaptive mode) and one output state, grown the same way.
+ *     Calls on one stream run in order; concurrent calls on different streams
+ *     use different slots.
  *   - HIP graph capture: pond_step (without stats) and pond_step_adjoint
  *     record kernels and device copies only, no memset.  Make one call on the
  *     capturing stream before capture (it allocates the stream's slot) and
@@ -130,9 +133,13 @@ int pond_moments(const pond_config* cfg, const pond_state* state, double* rho, d
 
 /*
  * Vector-Jacobian product of one pond_step (nsteps = 1) about the forward pass
- * in -> out_fwd.  out_fwd->iters must hold the pass counts written by that
- * forward step (the adjoint differentiates the computed map with these counts
- * fixed, i.e. the unrolled predictor-corrector iteration).
+ * in -> out_fwd, the unrolled predictor-corrector iteration differentiated
+ * with its pass counts fixed (the computed map).  The call first runs that
+ * step again from `in` with the same configuration, recording every node's
+ * pass gauges, densities and last-pass populations in the stream's scratch
+ * (the step is deterministic, so this run reproduces out_fwd bit for bit),
+ * then the adjoint kernel.  out_fwd is the caller's forward result; it must be
+ * given (with iters) but is not read.
  * adj_out: cotangents of (f, g) at t (adj_out->f is double in both precisions).
  * adj_in:  receives the cotangents of (f, g) at t - dt (double); it is
  *          overwritten, not accumulated.  Must not overlap the other buffers.

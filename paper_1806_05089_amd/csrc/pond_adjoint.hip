@@ -4,9 +4,8 @@
 // loop is unrolled with the pass count the forward step recorded per node, the
 // stencil origins floor(x) - 1 are held fixed, and the App. E test is not
 // differentiated.  Per node (one lane) the kernel
-//   1. recomputes the forward passes (the gauge lambda_k and density of every
-//      pass go to a small private array, the last pass's populations stay in
-//      registers);
+//   1. reads the pass history that the forward step recorded (the gauge
+//      lambda_k and density of every pass, the last pass's populations);
 //   2. runs the chain backwards: BGK (eq. 18), regauge (eq. 4), then for each
 //      pass the corrector moments (eqs. 10-12) and the advection (eqs. 5-6);
 //   3. adds the seed's cotangent (eqs. 7-8) to its own node.
@@ -37,6 +36,8 @@ struct AdjArgs {
   const void* f_in;
   const double* g_in;
   const uint8_t* iters;
+  const double* tape;    // pass history of the step (layout of StepArgs::tape)
+  const double* tape_f;  // last pass's populations of the step
   const double* af_out;  // [Q][N]
   const double* ag_out;  // [3][N]
   double* af_in;         // [Q][N], zeroed before the launch
@@ -197,136 +198,6 @@ __device__ __forceinline__ bool x_column(const XAxis<Q1>& x, int cc, int& rel, d
 
 __device__ __forceinline__ double pick4(const double* a, int m) {
   return m == 0 ? a[0] : m == 1 ? a[1] : m == 2 ? a[2] : a[3];
-}
-
-// Window part of a forward collocation point (staged values at element
-// offsets e, eh of the grouped window layout): the y contraction with the
-// G_{B->n} row gby, weighted by aym and added to hc.
-template <int Q1, int WN>
-__device__ __forceinline__ void fwd_window_point(const double* s_fB, int e, int eh, double aym,
-                                                 const double* gby, double* hc) {
-  constexpr int Q = Q1 * Q1;
-  double fs[Q];  // all loads first, so that they are in flight together
-  Win<Q1, double, WN>::load(s_fB, e, eh, fs);
-#pragma unroll
-  for (int ip = 0; ip < Q1; ++ip) {
-    double v = 0.0;
-#pragma unroll
-    for (int jp = 0; jp < Q1; ++jp) v = fma(gby[jp], fs[ip * Q1 + jp], v);
-    hc[ip] = fma(aym, v, hc[ip]);
-  }
-}
-
-// A forward collocation point outside the window: direct transform G_{s->n}
-// of the HBM state at (gx, gy), added to acc with the weights wx[i] * aym.
-template <int Q1, class FT, int WX, int WY, int WN>
-__device__ __forceinline__ void fwd_hbm_point(const Lane<Q1, FT, WX, WY, WN>& c, const Gauge& G,
-                                              int gx, int gy, double aym, const double* wx,
-                                              const LagRow& Pj, double inv_s, double* acc) {
-  using L = Lat<Q1>;
-  const AdjArgs& A = *c.A;
-  const FT* __restrict__ fin = static_cast<const FT*>(A.f_in);
-  const size_t src = (size_t)wrap_index(gy, A.ny, A.bc_y) * A.nx + wrap_index(gx, A.nx, A.bc_x);
-  double fs[Q1 * Q1];
-#pragma unroll
-  for (int p = 0; p < Q1 * Q1; ++p) fs[p] = double(fin[(size_t)p * c.plane + src]);
-  const double r = sqrt(A.g_in[2 * c.plane + src] * L::inv_TL) * inv_s;
-  const double dx = (A.g_in[src] - G.ux) * inv_s;
-  double gyr[Q1];
-  transfer_row_coef<Q1>(Pj, r, (A.g_in[c.plane + src] - G.uy) * inv_s, gyr);
-  double h[Q1];
-#pragma unroll
-  for (int ip = 0; ip < Q1; ++ip) {
-    double v = 0.0;
-#pragma unroll
-    for (int jp = 0; jp < Q1; ++jp) v = fma(gyr[jp], fs[ip * Q1 + jp], v);
-    h[ip] = v;
-  }
-#pragma unroll
-  for (int i = 0; i < Q1; ++i) {
-    double gxr[Q1];
-    transfer_row<Q1>(i, r, dx, gxr);
-    double v = 0.0;
-#pragma unroll
-    for (int ip = 0; ip < Q1; ++ip) v = fma(gxr[ip], h[ip], v);
-    acc[i] = fma(wx[i] * aym, v, acc[i]);
-  }
-}
-
-// Forward pass at gauge G: F[i*Q1+j] = advected populations (eqs. 5-6),
-// column by column as in the forward step (one read of each collocation
-// point per y speed, its y contraction shared by the x speeds).  A lane whose
-// four rows of the column lie in the window takes them in one straight run;
-// otherwise point by point, from LDS or HBM.
-template <int Q1, class FT, int WX, int WY, int WN>
-__device__ void forward_pass(const Lane<Q1, FT, WX, WY, WN>& c, const Gauge& G, double* F) {
-  using W = Win<Q1, double, WN>;
-  const double inv_s = 1.0 / G.s;
-  const double rB = c.sB * inv_s, dBx = (c.uxB - G.ux) * inv_s, dBy = (c.uyB - G.uy) * inv_s;
-  XAxis<Q1> x;
-  x_axis<Q1>(c.X, G, rB, dBx, x);
-#pragma unroll 1
-  for (int j = 0; j < Q1; ++j) {
-    const double yd = double(c.Y) - (G.s * speed_rt<Q1>(j) + G.uy);
-    const double fly = floor(yd);
-    double ay[4];
-    interp_weights(yd - (fly - 1.0), ay);
-    const int y0 = sat_floor_a(fly) - 1;
-    const int ly0 = y0 - c.wy0;
-    const bool rows_in = (unsigned)ly0 <= (unsigned)(WY - 4);
-    const LagRow Pj = lag_row<Q1>(j);
-    double gby[Q1];
-    transfer_row_coef<Q1>(Pj, rB, dBy, gby);
-    double acc[Q1];
-#pragma unroll
-    for (int i = 0; i < Q1; ++i) acc[i] = 0.0;
-#pragma unroll 1
-    for (int cc = 0; cc < x.ncol; ++cc) {
-      int rel;
-      double wx[Q1];
-      const bool need = x_column<Q1, false>(x, cc, rel, wx, nullptr);
-      if (!__any(need)) continue;
-      const int gx = c.X + rel, lx = gx - c.wx0;
-      // window rows: y contraction weighted and summed over the rows, the x
-      // rows of G_{B->n} applied once per column; HBM points point-wise
-      double hc[Q1];
-#pragma unroll
-      for (int ip = 0; ip < Q1; ++ip) hc[ip] = 0.0;
-      if (need && rows_in && (unsigned)lx < (unsigned)WX) {
-        const int e = (ly0 * WX + lx) * W::G;
-        int eh = e + W::NGH * W::GS;
-        asm volatile("" : "+v"(eh));
-#pragma unroll
-        for (int m = 0; m < 4; ++m)
-          fwd_window_point<Q1, WN>(c.s_fB, e + m * WX * W::G, eh + m * WX * W::G, pick4(ay, m),
-                                   gby, hc);
-      } else if (need) {
-#pragma unroll 1
-        for (int m = 0; m < 4; ++m) {
-          const int gy = y0 + m, ly = gy - c.wy0;
-          const double aym = pick4(ay, m);
-          if ((unsigned)lx < (unsigned)WX && (unsigned)ly < (unsigned)WY) {
-            const int e = (ly * WX + lx) * W::G;
-            fwd_window_point<Q1, WN>(c.s_fB, e, e + W::NGH * W::GS, aym, gby, hc);
-          } else {
-            fwd_hbm_point<Q1, FT, WX, WY, WN>(c, G, gx, gy, aym, wx, Pj, inv_s, acc);
-          }
-        }
-      }
-#pragma unroll
-      for (int i = 0; i < Q1; ++i) {
-        double v = 0.0;
-#pragma unroll
-        for (int ip = 0; ip < Q1; ++ip) v = fma(x.gbx[i][ip], hc[ip], v);
-        acc[i] = fma(wx[i], v, acc[i]);
-      }
-    }
-#pragma unroll
-    for (int i = 0; i < Q1; ++i)
-#pragma unroll
-      for (int jj = 0; jj < Q1; ++jj)
-        if (jj == j) F[i * Q1 + jj] = acc[i];
-  }
 }
 
 // Adjoint of a window collocation point for one row (staged values at
@@ -819,43 +690,21 @@ k_step_adjoint(AdjArgs A) {
       c.uyB = uyB;
       c.sB = sB;
 
-      // 1. forward recompute: gauges (and densities) of every pass
-      double hist_ux[kMaxPasses + 1], hist_uy[kMaxPasses + 1], hist_T[kMaxPasses + 1];
-      double hist_rho[kMaxPasses + 1];
-      double rhoK = 0.0;
+      // 1. pass history that the forward step recorded: the gauge lambda_k
+      // and density of every pass, and the last pass's populations
+      const double* __restrict__ tp = A.tape + node;
+      auto hist = [&](int k, int comp) { return tp[((size_t)k * 4 + comp) * plane]; };
+      const double rhoK = hist(K, 3);
       double F[Q];
-      hist_ux[0] = ux0;
-      hist_uy[0] = uy0;
-      hist_T[0] = T0;
-#pragma unroll 1
-      for (int k = 0; k < K; ++k) {
-        Gauge G{hist_ux[k], hist_uy[k], sqrt(hist_T[k] * L::inv_TL), hist_T[k]};
-        forward_pass<Q1, FT, WX, WY, WN>(c, G, F);
-        double rho = 0.0, mx = 0.0, my = 0.0, e2 = 0.0;
 #pragma unroll
-        for (int i = 0; i < Q1; ++i)
-#pragma unroll
-          for (int j = 0; j < Q1; ++j) {
-            const double fv = F[i * Q1 + j];
-            rho += fv;
-            mx = fma(L::c(i), fv, mx);
-            my = fma(L::c(j), fv, my);
-            e2 = fma(L::c(i) * L::c(i) + L::c(j) * L::c(j), fv, e2);
-          }
-        const double dux = G.s * mx / rho, duy = G.s * my / rho;
-        hist_ux[k + 1] = G.ux + dux;
-        hist_uy[k + 1] = G.uy + duy;
-        hist_T[k + 1] = A.isothermal ? G.T : 0.5 * (G.s * G.s * e2 / rho - (dux * dux + duy * duy));
-        hist_rho[k + 1] = rho;
-        rhoK = rho;
-      }
-      // F now holds the populations of the last pass, in gauge lambda_{K-1}.
+      for (int p = 0; p < Q; ++p) F[p] = A.tape_f[(size_t)p * plane + node];
+      // F holds the populations of the last pass, in gauge lambda_{K-1}.
 
       // 2a. BGK (eq. 18): f_out = f_reg + omega (rho W - f_reg)
       const double omega = 1.0 / A.tau;
-      const Gauge Gk{hist_ux[K - 1], hist_uy[K - 1], sqrt(hist_T[K - 1] * L::inv_TL),
-                     hist_T[K - 1]};
-      const Gauge G1{hist_ux[K], hist_uy[K], sqrt(hist_T[K] * L::inv_TL), hist_T[K]};
+      const Gauge Gk{hist(K - 1, 0), hist(K - 1, 1), sqrt(hist(K - 1, 2) * L::inv_TL),
+                     hist(K - 1, 2)};
+      const Gauge G1{hist(K, 0), hist(K, 1), sqrt(hist(K, 2) * L::inv_TL), hist(K, 2)};
       const double inv_s1 = 1.0 / G1.s;
       const double r = Gk.s * inv_s1;
       const double dx = (Gk.ux - G1.ux) * inv_s1, dy = (Gk.uy - G1.uy) * inv_s1;
@@ -960,13 +809,14 @@ k_step_adjoint(AdjArgs A) {
       // 2c. passes backwards: corrector moments, then advection
 #pragma unroll 1
       for (int k = K - 1; k >= 0; --k) {
-        const Gauge G{hist_ux[k], hist_uy[k], sqrt(hist_T[k] * L::inv_TL), hist_T[k]};
+        const double Tk = hist(k, 2);
+        const Gauge G{hist(k, 0), hist(k, 1), sqrt(Tk * L::inv_TL), Tk};
         // moments of pass k from its gauges (eqs. 10-12, peculiar frame)
-        const double dux = hist_ux[k + 1] - G.ux, duy = hist_uy[k + 1] - G.uy;
+        const double dux = hist(k + 1, 0) - G.ux, duy = hist(k + 1, 1) - G.uy;
         const double mxr = dux / G.s, myr = duy / G.s;  // mx / rho, my / rho
-        const double rho_k1 = hist_rho[k + 1];
+        const double rho_k1 = hist(k + 1, 3);
         const double e2r =
-            A.isothermal ? 0.0 : (2.0 * hist_T[k + 1] + dux * dux + duy * duy) / (G.s * G.s);
+            A.isothermal ? 0.0 : (2.0 * hist(k + 1, 2) + dux * dux + duy * duy) / (G.s * G.s);
         // cotangents of lambda_{k+1}
         double gux_n = gux_1, guy_n = guy_1, gT_n = gT_1, grho_n = rho_bar_next;
         double gux = gux_n, guy = guy_n, gs = 0.0, gT = 0.0;
@@ -1159,7 +1009,8 @@ hipError_t launch_adjoint_t(const AdjArgs& a, hipStream_t s) {
 }  // namespace
 
 hipError_t launch_adjoint(const pond_config& c, const void* f_in, const double* g_in,
-                          const uint8_t* iters, const double* adj_f_out, const double* adj_g_out,
+                          const uint8_t* iters, const double* tape, const double* tape_f,
+                          const double* adj_f_out, const double* adj_g_out,
                           double* adj_f_in, double* adj_g_in, double* adj_tau, TileQueue* queue,
                           hipStream_t s) {
   const size_t plane = (size_t)c.nx * c.ny;
@@ -1179,6 +1030,8 @@ hipError_t launch_adjoint(const pond_config& c, const void* f_in, const double* 
   a.f_in = f_in;
   a.g_in = g_in;
   a.iters = iters;
+  a.tape = tape;
+  a.tape_f = tape_f;
   a.af_out = adj_f_out;
   a.ag_out = adj_g_out;
   a.af_in = adj_f_in;

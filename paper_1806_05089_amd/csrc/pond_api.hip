@@ -26,10 +26,12 @@ int hip_fail(hipError_t e, const char* where) {
 }
 
 // Device memory kept per (device, stream): step statistics, the step
-// kernel's tile queue, and the tile cost keys and tile order that one step
-// leaves for the next.  Work on one stream runs in order, so a slot is never
-// used by two kernels at once.  Allocated on the first call on a stream (the
-// tile arrays grow with the grid) and held until the process ends.
+// kernel's tile queue, the tile cost keys and tile order that one step leaves
+// for the next, and the adjoint's scratch (the pass history of the step it
+// differentiates and that step's output state).  Work on one stream runs in
+// order, so a slot is never used by two kernels at once.  Allocated on the
+// first call on a stream (the arrays grow with the grid) and held until the
+// process ends.
 struct Slot {
   pond::StreamSlot* dev = nullptr;
   uint16_t* keys = nullptr;
@@ -37,6 +39,8 @@ struct Slot {
   size_t cap = 0;           // tiles the arrays hold
   int order_nx = -1;        // grid whose tile order `order` holds
   int order_ny = -1;
+  void* adj_mem = nullptr;  // adjoint scratch, adj_cap bytes
+  size_t adj_cap = 0;
 };
 std::mutex g_mutex;
 std::map<std::pair<int, void*>, Slot> g_slots;
@@ -89,6 +93,26 @@ int ensure_tile_arrays(Slot* sl, size_t ntiles, hipStream_t s) {
   return POND_OK;
 }
 
+// Adjoint scratch of `bytes` bytes.  Growing it waits for the stream, since a
+// kernel in flight may still use the old memory.
+int ensure_adjoint_scratch(Slot* sl, size_t bytes, hipStream_t s) {
+  if (sl->adj_cap >= bytes) return POND_OK;
+  hipError_t e;
+  if (sl->adj_cap) {
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "pond_step_adjoint sync");
+    (void)hipFree(sl->adj_mem);
+    sl->adj_mem = nullptr;
+    sl->adj_cap = 0;
+  }
+  e = hipMalloc(&sl->adj_mem, bytes);
+  if (e != hipSuccess) {
+    sl->adj_mem = nullptr;
+    return hip_fail(e, "hipMalloc(adjoint scratch)");
+  }
+  sl->adj_cap = bytes;
+  return POND_OK;
+}
+
 // Passes a node runs one lane per node before an unconverged node moves to the
 // block's 16-lane tail (POND_BULK_CAP overrides the default).
 int bulk_cap(int precision) {
@@ -133,6 +157,52 @@ int check_config(const pond_config* c) {
   if (!(c->eps_abs >= 0.0) || !(c->eps_rel >= 0.0))
     return fail(POND_E_INVALID, "eps_abs and eps_rel must be >= 0");
   return POND_OK;
+}
+
+// Arguments of one step launch on a slot's queue and tile arrays (the state
+// buffers, counters and pass history are set by the caller).
+pond::StepArgs step_args(const pond_config& c, Slot* slot) {
+  pond::StepArgs a;
+  a.nx = c.nx;
+  a.ny = c.ny;
+  a.bc_x = c.bc_x;
+  a.bc_y = c.bc_y;
+  a.max_iter = c.max_iter;
+  a.fixed_iter = c.fixed_iter;
+  a.seed_mode = c.seed_mode;
+  a.isothermal = c.isothermal;
+  a.bulk_cap = bulk_cap(c.precision);
+  a.tau = c.tau;
+  a.eps_abs = c.eps_abs;
+  a.eps_rel = c.eps_rel;
+  a.f_in = nullptr;
+  a.g_in = nullptr;
+  a.f_out = nullptr;
+  a.g_out = nullptr;
+  a.iters = nullptr;
+  a.counters = nullptr;
+  a.queue = &slot->dev->queue;
+  a.tile_keys = slot->keys;
+  a.tile_order = nullptr;
+  a.tile_order_next = slot->order;
+  a.tape = nullptr;
+  a.tape_f = nullptr;
+  return a;
+}
+
+// Launches one step; the tile order left by the previous step on the stream is
+// used when it belongs to the same grid.
+hipError_t launch_step_on(const pond_config& c, Slot* slot, pond::StepArgs& a, hipStream_t s) {
+  const bool ordered = slot->order_nx == c.nx && slot->order_ny == c.ny;
+  a.tile_order = ordered ? slot->order : nullptr;
+  const hipError_t e = pond::launch_step(c, a, s);
+  if (e != hipSuccess) {
+    slot->order_nx = slot->order_ny = -1;
+    return e;
+  }
+  slot->order_nx = c.nx;
+  slot->order_ny = c.ny;
+  return hipSuccess;
 }
 
 }  // namespace
@@ -189,23 +259,8 @@ int pond_step(const pond_config* cfg, const pond_state* in, pond_state* out, int
   pond::StepCounters* cnt = stats ? &slot->dev->counters : nullptr;
   if ((rc = ensure_tile_arrays(slot, pond::step_tile_count(*cfg), s))) return rc;
 
-  pond::StepArgs a;
-  a.nx = cfg->nx;
-  a.ny = cfg->ny;
-  a.bc_x = cfg->bc_x;
-  a.bc_y = cfg->bc_y;
-  a.max_iter = cfg->max_iter;
-  a.fixed_iter = cfg->fixed_iter;
-  a.seed_mode = cfg->seed_mode;
-  a.isothermal = cfg->isothermal;
-  a.bulk_cap = bulk_cap(cfg->precision);
-  a.tau = cfg->tau;
-  a.eps_abs = cfg->eps_abs;
-  a.eps_rel = cfg->eps_rel;
+  pond::StepArgs a = step_args(*cfg, slot);
   a.iters = out->iters;
-  a.queue = &slot->dev->queue;
-  a.tile_keys = slot->keys;
-  a.tile_order_next = slot->order;
 
   const void* src_f = in->f;
   const double* src_g = in->g;
@@ -220,21 +275,12 @@ int pond_step(const pond_config* cfg, const pond_state* in, pond_state* out, int
     a.f_out = dst_f;
     a.g_out = dst_g;
     a.counters = (last && cnt) ? cnt : nullptr;
-    // the previous step on this stream left a tile order for this grid
-    const bool ordered = slot->order_nx == cfg->nx && slot->order_ny == cfg->ny;
-    a.tile_order = ordered ? slot->order : nullptr;
     if (a.counters) {
       e = pond::launch_zero_u64(reinterpret_cast<unsigned long long*>(cnt), 4, s);
       if (e != hipSuccess) return hip_fail(e, "pond_step zero counters");
     }
-
-    e = pond::launch_step(*cfg, a, s);
-    if (e != hipSuccess) {
-      slot->order_nx = slot->order_ny = -1;
-      return hip_fail(e, "pond_step launch");
-    }
-    slot->order_nx = cfg->nx;
-    slot->order_ny = cfg->ny;
+    e = launch_step_on(*cfg, slot, a, s);
+    if (e != hipSuccess) return hip_fail(e, "pond_step launch");
     src_f = dst_f;
     src_g = dst_g;
   }
@@ -288,9 +334,36 @@ int pond_step_adjoint(const pond_config* cfg, const pond_state* in, const pond_s
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   Slot* slot = nullptr;
   if ((rc = slot_for_stream(s, &slot))) return rc;
-  hipError_t e = pond::launch_adjoint(*cfg, in->f, in->g, out_fwd->iters, (const double*)adj_out->f,
-                                      adj_out->g, (double*)adj_in->f, adj_in->g, adj_tau,
-                                      &slot->dev->queue, s);
+  if ((rc = ensure_tile_arrays(slot, pond::step_tile_count(*cfg), s))) return rc;
+  // The step is run again with its pass history recorded (it reproduces
+  // out_fwd bit for bit); scratch: history, last populations, output state.
+  const int kslots = 1 + (cfg->fixed_iter > 0 ? cfg->fixed_iter : cfg->max_iter);
+  const size_t q = (size_t)cfg->q1d * cfg->q1d;
+  const size_t tape_b = (size_t)kslots * 4 * plane * sizeof(double);
+  const size_t tapef_b = q * plane * sizeof(double);
+  const size_t align = 256;
+  auto up = [&](size_t b) { return (b + align - 1) / align * align; };
+  const size_t total = up(tape_b) + up(tapef_b) + up(fb) + up(agb) + up(plane);
+  if ((rc = ensure_adjoint_scratch(slot, total, s))) return rc;
+  char* m = static_cast<char*>(slot->adj_mem);
+  double* tape = reinterpret_cast<double*>(m);
+  double* tape_f = reinterpret_cast<double*>(m + up(tape_b));
+  void* sf = m + up(tape_b) + up(tapef_b);
+  double* sg = reinterpret_cast<double*>(m + up(tape_b) + up(tapef_b) + up(fb));
+  uint8_t* siters = reinterpret_cast<uint8_t*>(m + up(tape_b) + up(tapef_b) + up(fb) + up(agb));
+  pond::StepArgs a = step_args(*cfg, slot);
+  a.f_in = in->f;
+  a.g_in = in->g;
+  a.f_out = sf;
+  a.g_out = sg;
+  a.iters = siters;
+  a.tape = tape;
+  a.tape_f = tape_f;
+  hipError_t e = launch_step_on(*cfg, slot, a, s);
+  if (e != hipSuccess) return hip_fail(e, "pond_step_adjoint step launch");
+  e = pond::launch_adjoint(*cfg, in->f, in->g, siters, tape, tape_f, (const double*)adj_out->f,
+                           adj_out->g, (double*)adj_in->f, adj_in->g, adj_tau, &slot->dev->queue,
+                           s);
   if (e == hipErrorNotSupported) return fail(POND_E_UNSUPPORTED, "pond_step_adjoint: not available");
   if (e != hipSuccess) return hip_fail(e, "pond_step_adjoint launch");
   return POND_OK;

@@ -53,6 +53,14 @@ struct StepArgs {
   uint16_t* tile_keys;
   const unsigned* tile_order;
   unsigned* tile_order_next;
+  // Pass history for the adjoint (nullable, both or neither).  With N nodes,
+  // tape[(k * 4 + c) * N + node] holds for k = 0 the seed gauge (c = 0, 1, 2:
+  // u_x, u_y, T) and for k >= 1 the gauge after pass k (c = 0, 1, 2) and the
+  // density of pass k (c = 3), for k up to the node's pass count (at most
+  // max_iter, or fixed_iter); tape_f[p * N + node] holds population p of the
+  // node's last pass, in the gauge of that pass.  Bad nodes leave it unset.
+  double* tape;
+  double* tape_f;
 };
 
 hipError_t launch_init(const pond_config& c, const double* rho, const double* ux,
@@ -63,9 +71,11 @@ unsigned step_tile_count(const pond_config& c);
 hipError_t launch_moments(const pond_config& c, const void* f, const double* g, double* rho,
                           double* ux, double* uy, double* T, double* Mmn, hipStream_t s);
 hipError_t launch_zero_u64(unsigned long long* p, int n, hipStream_t s);
+// Adjoint of one step; iters, tape and tape_f are the pass counts and the
+// pass history that a step with the same input and configuration recorded.
 hipError_t launch_adjoint(const pond_config& c, const void* f_in, const double* g_in,
-                          const uint8_t* iters, const double* adj_f_out, const double* adj_g_out,
-                          double* adj_f_in, double* adj_g_in, double* adj_tau, TileQueue* queue,
-                          hipStream_t s);
+                          const uint8_t* iters, const double* tape, const double* tape_f,
+                          const double* adj_f_out, const double* adj_g_out, double* adj_f_in,
+                          double* adj_g_in, double* adj_tau, TileQueue* queue, hipStream_t s);
 
 }  // namespace pond

@@ -398,6 +398,13 @@ __device__ __forceinline__ void tail_group(const StepArgs& A, const FT* s_f, int
                                         double(v[1]) + double(er[1]), double(v[2]) + double(er[2]),
                                         double(v[3]) + double(er[3]), passes, rho1, ux1, uy1, T1,
                                         flags);
+      if (verdict != kBad && A.tape && p == 0) {
+        const size_t t = (size_t)passes * 4 * plane + node;
+        A.tape[t] = ux1;
+        A.tape[t + plane] = uy1;
+        A.tape[t + 2 * plane] = T1;
+        A.tape[t + 3 * plane] = rho1;
+      }
       if (verdict == kBad) {
         bad = true;
         gdone = true;
@@ -430,6 +437,7 @@ __device__ __forceinline__ void tail_group(const StepArgs& A, const FT* s_f, int
       if (pop) store_bad<Q1, FT>(A, fout, plane, node, p, p + 1);
       flags |= POND_ITERS_BAD;
     } else if (pop) {
+      if (A.tape_f) A.tape_f[(size_t)p * plane + node] = double(fij);
       const FT feq = FT(rho1 * (L::w(pi) * L::w(pj)));
       fout[(size_t)p * plane + node] = fr + FT(1.0 / A.tau) * (feq - fr);
       if (p == 0) {
@@ -543,6 +551,11 @@ k_step(StepArgs A) {
       } else if (A.seed_mode == 2) {
         ux = -ux;
         uy = -uy;
+      }
+      if (A.tape) {
+        A.tape[node] = ux;
+        A.tape[plane + node] = uy;
+        A.tape[2 * plane + node] = T;
       }
     }
 
@@ -783,6 +796,13 @@ k_step(StepArgs A) {
           bad = true;
           break;
         }
+        if (A.tape) {
+          const size_t t = (size_t)passes * 4 * plane + node;
+          A.tape[t] = ux1;
+          A.tape[t + plane] = uy1;
+          A.tape[t + 2 * plane] = T1;
+          A.tape[t + 3 * plane] = rho1;
+        }
         if (verdict == kDone) break;
         ux = ux1;
         uy = uy1;
@@ -798,6 +818,10 @@ k_step(StepArgs A) {
           store_bad<Q1, FT>(A, fout, plane, node, 0, Q);
           flags |= POND_ITERS_BAD;
         } else {
+          if (A.tape_f) {
+#pragma unroll
+            for (int p = 0; p < Q; ++p) A.tape_f[(size_t)p * plane + node] = double(ft[p]);
+          }
           // a8: f^{lambda_n} -> lambda_{n+1}, one full Kronecker transform.
           const double s = sqrt(T * L::inv_TL), s1 = sqrt(T1 * L::inv_TL);
           const double inv_s1 = 1.0 / s1, r = s * inv_s1;
