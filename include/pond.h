@@ -26,9 +26,9 @@
  *   - Library-held device memory: the first pond_init / pond_step /
  *     pond_step_adjoint on a (device, stream) pair allocates and zeroes a small
  *     slot for it (step statistics, the step kernel's tile queue, and one cost
- *     key and one order entry per 32 x 16 tile, grown after a stream
- *     synchronisation when a larger grid appears); it is held until the
- *     process ends.  A step leaves its tiles' costs there, and the next step
+ *     key and one order entry per tile of 32 x 16 nodes, 32 x 8 in FP32-mixed
+ *     mode, grown after a stream synchronisation when a larger grid appears);
+ *     it is held until the process ends.  A step leaves its tiles' costs there, and the next step
  *     on the same stream takes the costliest tiles first; results do not
  *     depend on that order.  pond_step_adjoint also keeps its scratch there:
  *     ((K + 1) * 4 + q1d^2) * nx * ny doubles of pass history (K = fixed_iter,

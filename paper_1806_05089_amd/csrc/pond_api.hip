@@ -37,8 +37,9 @@ struct Slot {
   uint16_t* keys = nullptr;
   unsigned* order = nullptr;
   size_t cap = 0;           // tiles the arrays hold
-  int order_nx = -1;        // grid whose tile order `order` holds
+  int order_nx = -1;        // grid and tile count whose tile order `order` holds
   int order_ny = -1;
+  unsigned order_tiles = 0;
   void* adj_mem = nullptr;  // adjoint scratch, adj_cap bytes
   size_t adj_cap = 0;
 };
@@ -191,9 +192,12 @@ pond::StepArgs step_args(const pond_config& c, Slot* slot) {
 }
 
 // Launches one step; the tile order left by the previous step on the stream is
-// used when it belongs to the same grid.
+// used when it belongs to the same grid and tile shape (the tile shape depends
+// on the precision).
 hipError_t launch_step_on(const pond_config& c, Slot* slot, pond::StepArgs& a, hipStream_t s) {
-  const bool ordered = slot->order_nx == c.nx && slot->order_ny == c.ny;
+  const unsigned ntiles = pond::step_tile_count(c);
+  const bool ordered =
+      slot->order_nx == c.nx && slot->order_ny == c.ny && slot->order_tiles == ntiles;
   a.tile_order = ordered ? slot->order : nullptr;
   const hipError_t e = pond::launch_step(c, a, s);
   if (e != hipSuccess) {
@@ -202,6 +206,7 @@ hipError_t launch_step_on(const pond_config& c, Slot* slot, pond::StepArgs& a, h
   }
   slot->order_nx = c.nx;
   slot->order_ny = c.ny;
+  slot->order_tiles = ntiles;
   return hipSuccess;
 }
 

@@ -458,39 +458,41 @@ __device__ __forceinline__ void tail_group(const StepArgs& A, const FT* s_f, int
 }
 
 // Tile cost keys: the sum over the tile's waves of the most passes a node of
-// the wave took (at most 8 waves x 63 passes).
-constexpr unsigned kKeyBins = 512;
+// the wave took.  One key bin per thread of the block: NT / 64 waves of at
+// most 63 passes keep the keys below NT.
+template <int NT>
+constexpr unsigned kKeyBins = NT;
 
 // Counting sort of the tiles by key, largest first, into order[] (one block,
-// NT threads, 3 kKeyBins words of LDS).  Tiles with equal keys land in any
+// NT threads, 3 NT words of LDS).  Tiles with equal keys land in any
 // order; the step's results do not depend on the order of its tiles.
 template <int NT>
 __device__ void order_tiles(const uint16_t* keys, unsigned* order, unsigned ntiles,
                             unsigned* lds) {
-  static_assert(NT >= (int)kKeyBins, "one thread per key bin");
+  static_assert(NT >= (int)kKeyBins<NT>, "one thread per key bin");
   unsigned* hist = lds;
-  unsigned* scan = lds + kKeyBins;
-  unsigned* start = lds + 2 * kKeyBins;
+  unsigned* scan = lds + kKeyBins<NT>;
+  unsigned* start = lds + 2 * kKeyBins<NT>;
   const int tid = threadIdx.x;
-  if (tid < (int)kKeyBins) hist[tid] = 0u;
+  if (tid < (int)kKeyBins<NT>) hist[tid] = 0u;
   __syncthreads();
   for (unsigned t = tid; t < ntiles; t += NT) atomicAdd(&hist[keys[t]], 1u);
   __syncthreads();
   // inclusive scan over bins in decreasing key order (Hillis-Steele)
-  unsigned v = tid < (int)kKeyBins ? hist[kKeyBins - 1 - tid] : 0u;
-  for (unsigned off = 1; off < kKeyBins; off <<= 1) {
-    if (tid < (int)kKeyBins) scan[tid] = v;
+  unsigned v = tid < (int)kKeyBins<NT> ? hist[kKeyBins<NT> - 1 - tid] : 0u;
+  for (unsigned off = 1; off < kKeyBins<NT>; off <<= 1) {
+    if (tid < (int)kKeyBins<NT>) scan[tid] = v;
     __syncthreads();
-    if (tid < (int)kKeyBins && (unsigned)tid >= off) v += scan[tid - off];
+    if (tid < (int)kKeyBins<NT> && (unsigned)tid >= off) v += scan[tid - off];
     __syncthreads();
   }
-  if (tid < (int)kKeyBins) start[kKeyBins - 1 - tid] = v - hist[kKeyBins - 1 - tid];
+  if (tid < (int)kKeyBins<NT>) start[kKeyBins<NT> - 1 - tid] = v - hist[kKeyBins<NT> - 1 - tid];
   __syncthreads();
   for (unsigned t = tid; t < ntiles; t += NT) order[atomicAdd(&start[keys[t]], 1u)] = t;
 }
 
 template <int Q1, class FT, int TX, int TY, int H>
-__global__ void __launch_bounds__(TX * TY)
+__global__ void __launch_bounds__(TX * TY, sizeof(FT) == 8 ? 2 : 3)
 k_step(StepArgs A) {
   constexpr int Q = Q1 * Q1;
   using L = Lat<Q1>;
@@ -932,7 +934,8 @@ k_step(StepArgs A) {
         key += s_wmax[w];
         s_wmax[w] = 0u;
       }
-      if (A.tile_keys) A.tile_keys[tile] = (uint16_t)(key < kKeyBins ? key : kKeyBins - 1);
+      if (A.tile_keys)
+        A.tile_keys[tile] = (uint16_t)(key < kKeyBins<NT> ? key : kKeyBins<NT> - 1);
     }
   }  // tile loop
 
@@ -955,21 +958,15 @@ k_step(StepArgs A) {
   }
 }
 
-// Tile shapes (TX x TY nodes per block, halo H).  D2Q16: 32 x 16 nodes with a
-// 42 x 26 window: 140 KiB of LDS in FP64 (one block, 8 waves per CU) and
-// 70 KiB in FP32 (two blocks per CU).
-#ifndef POND_TILE_X
-#define POND_TILE_X 32
-#endif
-#ifndef POND_TILE_Y
-#define POND_TILE_Y 16
-#endif
-#ifndef POND_HALO
-#define POND_HALO 5
-#endif
+// Tile shapes (TX x TY nodes per block, halo H).  FP64: 32 x 16 nodes, for
+// D2Q16 a 42 x 26 window of 140 KiB of LDS (one block of 8 waves per CU, 2
+// waves per SIMD).  FP32-mixed: 32 x 8 nodes, a 42 x 18 window of 48 KiB,
+// three blocks of 4 waves per CU (registers capped at 168 per lane for 3
+// waves per SIMD; measured 7 % faster than 32 x 16 blocks at 2 waves per
+// SIMD, the spills included).
 template <int Q1, class FT>
 struct StepTile {
-  static constexpr int TX = POND_TILE_X, TY = POND_TILE_Y, H = Q1 == 4 ? POND_HALO : 4;
+  static constexpr int TX = 32, TY = sizeof(FT) == 8 ? 16 : 8, H = Q1 == 4 ? 5 : 4;
 };
 
 // Persistent grid: as many blocks as the device holds at once (CUs x blocks
@@ -1001,12 +998,16 @@ hipError_t launch_step_t(const StepArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <class FT>
+unsigned tile_count_t(const pond_config& c) {
+  using ST = StepTile<4, FT>;  // both lattices use the same tile shape
+  return (unsigned)(((c.nx + ST::TX - 1) / ST::TX) * (long long)((c.ny + ST::TY - 1) / ST::TY));
+}
+
 }  // namespace
 
 unsigned step_tile_count(const pond_config& c) {
-  // every variant uses the same tile shape
-  using ST = StepTile<4, double>;
-  return (unsigned)(((c.nx + ST::TX - 1) / ST::TX) * (long long)((c.ny + ST::TY - 1) / ST::TY));
+  return c.precision == POND_F64 ? tile_count_t<double>(c) : tile_count_t<float>(c);
 }
 
 hipError_t launch_step(const pond_config& c, const StepArgs& a, hipStream_t s) {

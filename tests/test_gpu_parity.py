@@ -314,6 +314,26 @@ def test_tile_order_multi_step_ragged(gpu):
     assert torch.equal(st.g, torch.from_numpy(gg).to(st.g.device))
 
 
+def test_tile_order_precision_switch(gpu):
+    """FP32-mixed and FP64 steps use different tile shapes (32 x 8 and 32 x 16):
+    alternating them on one stream and grid must not hand one precision the
+    tile order the other left (every tile is still computed exactly once, so
+    the FP32-mixed run repeats bit for bit)."""
+    w = workloads.riemann2d(96, seed=3)
+    c32 = _cfg(w, precision=pond.POND_F32_MIXED, max_iter=20, eps_abs=1e-6, eps_rel=1e-5)
+    c64 = _cfg(w, max_iter=20)
+    runs = []
+    for _ in range(2):
+        st = pond.init(c32, w.rho, w.ux, w.uy, w.T)
+        out, _ = pond.step(c32, st, nsteps=3)
+        runs.append((out.f.clone(), out.g.clone(), out.iters.clone()))
+        s64 = pond.init(c64, w.rho, w.ux, w.uy, w.T)
+        pond.step(c64, s64, nsteps=3)
+    for a, b in zip(runs[0], runs[1]):
+        assert torch.equal(a, b)
+    assert int((runs[0][2] & pond.POND_ITERS_MASK).min()) >= 1
+
+
 def test_adaptive_results_independent_of_tile_order(gpu):
     """The same adaptive run twice on one stream: the second run starts from
     the tile order the first left behind, and must agree bit for bit."""
