@@ -170,15 +170,22 @@ __device__ __forceinline__ double speed_rt(int i) {
 // ----------------------------------------------- reconstruction (App. C)
 // Third-order Lagrange weights on the four collocation points x0 + n,
 // x0 = floor(x) - 1, at local coordinate t = x - x0 in [1, 2).
-// Weight of column n of a stencil, zero for n outside 0..3: the same products
-// as interp_weight_at, the constant factor zeroed outside.  The factor is a
-// sign and a magnitude picked by two-way selects (a four-way chain on n is
-// compiled into branches).
-__device__ __forceinline__ double interp_weight_masked(int n, double t) {
+// Weight of stencil node n (0..3) for a per-lane n: the same products as
+// interp_weight_at, the constant factor a sign and a magnitude picked by
+// two-way selects (a four-way chain on n is compiled into branches).
+__device__ __forceinline__ double interp_weight_sel(int n, double t) {
   const double e1 = t - (n == 0 ? 1.0 : 0.0);
   const double e2 = t - (n <= 1 ? 2.0 : 1.0);
   const double e3 = t - (n <= 2 ? 3.0 : 2.0);
   const double mag = ((n + 1) & 2) == 0 ? 1.0 / 6.0 : 0.5;  // nodes 0, 3 : 1, 2
+  return e1 * e2 * e3 * ((n & 1) ? mag : -mag);
+}
+// The same, zero for n outside 0..3, without a branch.
+__device__ __forceinline__ double interp_weight_masked(int n, double t) {
+  const double e1 = t - (n == 0 ? 1.0 : 0.0);
+  const double e2 = t - (n <= 1 ? 2.0 : 1.0);
+  const double e3 = t - (n <= 2 ? 3.0 : 2.0);
+  const double mag = ((n + 1) & 2) == 0 ? 1.0 / 6.0 : 0.5;
   const double cn = (n & 1) ? mag : -mag;
   return e1 * e2 * e3 * ((unsigned)n < 4u ? cn : 0.0);
 }

@@ -741,7 +741,7 @@ k_step(StepArgs A) {
               // FP64: a wave skips the weight of a speed none of its lanes
               // needs (measured faster); FP32: branch-free
               if constexpr (sizeof(FT) == 8)
-                wx[i] = in ? FT(interp_weight_at(n, tx[i])) : FT(0);
+                wx[i] = in ? FT(interp_weight_sel(n, tx[i])) : FT(0);
               else
                 wx[i] = FT(interp_weight_masked(n, tx[i]));
               need = need || in;
