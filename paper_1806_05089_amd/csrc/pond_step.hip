@@ -365,14 +365,39 @@ __device__ __forceinline__ void tail_group(const StepArgs& A, const FT* s_f, int
       row_to<Q1, FT>(Pi, rB, (uxB - ux) * inv_s, gbx);
       row_to<Q1, FT>(Pj, rB, (uyB - uy) * inv_s, gby);
       FT acc = FT(0);
+      using W = Win<Q1, FT, WN>;
+      const int ly0 = y0 - wy0;
+      const bool rows_in = (unsigned)ly0 <= (unsigned)(WY - 4);
 #pragma unroll 1
       for (int n = 0; n < 4; ++n) {
         const double axn = n == 0 ? ax[0] : n == 1 ? ax[1] : n == 2 ? ax[2] : ax[3];
         FT col = FT(0);
+        const int lx = x0 + n - wx0;
+        if (rows_in && (unsigned)lx < (unsigned)WX) {
+          // the column's four rows inside the window: one straight run
+          const int e = (ly0 * WX + lx) * W::G;
+          int eh = e + W::NGH * W::GS;
+          asm volatile("" : "+v"(eh));
 #pragma unroll
-        for (int m = 0; m < 4; ++m)
-          col += FT(ay[m]) * pair_value<Q1, FT, WX, WY, WN>(A, s_f, wx0, wy0, x0 + n, y0 + m, gbx,
-                                                            gby, Pi, Pj, ux, uy, inv_s);
+          for (int m = 0; m < 4; ++m) {
+            FT f[Q];
+            W::load(s_f, e + m * WX * W::G, eh + m * WX * W::G, f);
+            FT t = FT(0);
+#pragma unroll
+            for (int ip = 0; ip < Q1; ++ip) {
+              FT h = FT(0);
+#pragma unroll
+              for (int jp = 0; jp < Q1; ++jp) h += gby[jp] * f[ip * Q1 + jp];
+              t += gbx[ip] * h;
+            }
+            col += FT(ay[m]) * t;
+          }
+        } else {
+#pragma unroll
+          for (int m = 0; m < 4; ++m)
+            col += FT(ay[m]) * pair_value<Q1, FT, WX, WY, WN>(A, s_f, wx0, wy0, x0 + n, y0 + m,
+                                                              gbx, gby, Pi, Pj, ux, uy, inv_s);
+        }
         acc += FT(axn) * col;
       }
       fij = pop ? acc : FT(0);
