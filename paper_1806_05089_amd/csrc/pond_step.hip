@@ -13,10 +13,10 @@
 // collocation point s into the node's gauge lambda_n is G_{B->n} applied to
 // the staged f^B_s: the per-axis factors of G_{B->n} are built once per node
 // and pass.  A wave walks the union of its lanes' stencil columns (relative
-// to each lane's node) once per y speed; a column's four rows are read from
-// LDS once, contracted with the y row of G_{B->n} and summed with their y
-// weights, and the four x speeds share the result.  A collocation point outside the window is read from HBM
-// and transformed directly with G_{s->n}.  After staging the lanes iterate
+// to each lane's node); per y speed a column's four rows are read from LDS,
+// contracted with the y row of G_{B->n} and summed with their y weights, and
+// the four x speeds share the result.  A collocation point outside the window
+// is read from HBM and transformed directly with G_{s->n}.  After staging the lanes iterate
 // independently (no further barriers).
 #include <hip/hip_runtime.h>
 #include <limits.h>
@@ -732,29 +732,43 @@ k_step(StepArgs A) {
           deferred = true;
           break;
         }
-        // The wave walks the union of its lanes' stencil columns once per y
-        // speed; every collocation point of a column is read from LDS once and
-        // its y contraction is shared by the four x speeds (each with its own
-        // weight, zero where the column is outside that speed's stencil).
+        // The wave walks the union of its lanes' stencil columns (the same for
+        // every y speed); every collocation point of a column is read from LDS
+        // once per y speed and its y contraction is shared by the four x
+        // speeds (each with its own weight, zero where the column is outside
+        // that speed's stencil).
         if (!wave_column_range(lo, hi, has, lo, hi)) hi = lo - 1;
+        // y speeds per column walk: FP64 takes two (the column's weights,
+        // tests and addresses serve both; measured faster), FP32 one (the
+        // extra registers cost it more than it saves)
+        constexpr int JB = (sizeof(FT) == 8 && Q1 % 2 == 0) ? 2 : 1;
 #pragma unroll 1
-        for (int j = 0; j < Q1; ++j) {
-          // a2 + a3 (y axis): the departure ordinate depends on c_j only.
-          const double yd = double(Y) - (s * speed_rt<Q1>(j) + uy);
-          const double fly = floor(yd);
-          const double ty = yd - (fly - 1.0);
-          FT ayw[4];
+        for (int j0 = 0; j0 < Q1; j0 += JB) {
+          FT ayw[JB][4];
+          int y0[JB], ly0[JB];
+          bool rows_in[JB];
+          LagRow Pj[JB];
+          FT gby[JB][Q1];
+          FT acc_row[JB][Q1];
+          bool all_in = true;
 #pragma unroll
-          for (int m = 0; m < 4; ++m) ayw[m] = FT(interp_weight_at(m, ty));
-          const int y0 = sat_floor(fly) - 1;
-          const int ly0 = y0 - wy0;
-          const bool rows_in = (unsigned)ly0 <= (unsigned)(WY - 4);
-          const LagRow Pj = lag_row<Q1>(j);
-          FT gby[Q1];
-          row_to<Q1, FT>(Pj, rB, dBy, gby);
-          FT acc_row[Q1];
+          for (int b = 0; b < JB; ++b) {
+            // a2 + a3 (y axis): the departure ordinate depends on c_j only.
+            const int j = j0 + b;
+            const double yd = double(Y) - (s * speed_rt<Q1>(j) + uy);
+            const double fly = floor(yd);
+            const double ty = yd - (fly - 1.0);
 #pragma unroll
-          for (int i = 0; i < Q1; ++i) acc_row[i] = FT(0);
+            for (int m = 0; m < 4; ++m) ayw[b][m] = FT(interp_weight_at(m, ty));
+            y0[b] = sat_floor(fly) - 1;
+            ly0[b] = y0[b] - wy0;
+            rows_in[b] = (unsigned)ly0[b] <= (unsigned)(WY - 4);
+            all_in = all_in && rows_in[b];
+            Pj[b] = lag_row<Q1>(j);
+            row_to<Q1, FT>(Pj[b], rB, dBy, gby[b]);
+#pragma unroll
+            for (int i = 0; i < Q1; ++i) acc_row[b][i] = FT(0);
+          }
 #pragma unroll 1
           for (int rel = lo; rel <= hi; ++rel) {
             FT wx[Q1];
@@ -772,35 +786,54 @@ k_step(StepArgs A) {
               need = need || in;
             }
             if (!__any(need)) continue;
-            FT hc[Q1];  // y-contracted window values, summed over the rows
+            FT hc[JB][Q1];
 #pragma unroll
-            for (int ip = 0; ip < Q1; ++ip) hc[ip] = FT(0);
+            for (int b = 0; b < JB; ++b)
+#pragma unroll
+              for (int ip = 0; ip < Q1; ++ip) hc[b][ip] = FT(0);
             const int lx = X + rel - wx0;
-            if (need && rows_in && (unsigned)lx < (unsigned)WX) {
-              window_column<Q1, FT, WX, WN>(s_f, ly0 * WX + lx, ayw, gby, hc);
+            const bool col_in = (unsigned)lx < (unsigned)WX;
+            if (need && all_in && col_in) {
+#pragma unroll
+              for (int b = 0; b < JB; ++b)
+                window_column<Q1, FT, WX, WN>(s_f, ly0[b] * WX + lx, ayw[b], gby[b], hc[b]);
             } else if (need) {
-              // a column that leaves the window: point by point, LDS or HBM
+#pragma unroll
+              for (int b = 0; b < JB; ++b) {
+                // with one speed per walk this path means the column leaves the window
+                if (JB > 1 && rows_in[b] && col_in) {
+                  window_column<Q1, FT, WX, WN>(s_f, ly0[b] * WX + lx, ayw[b], gby[b], hc[b]);
+                } else {
 #pragma unroll 1
-              for (int m = 0; m < 4; ++m) {
-                const FT aym = m == 0 ? ayw[0] : m == 1 ? ayw[1] : m == 2 ? ayw[2] : ayw[3];
-                column_point<Q1, FT, WX, WY, WN>(A, s_f, wx0, wy0, X + rel, y0 + m, true, aym,
-                                                 wx, gby, Pj, ux, uy, inv_s, hc, acc_row);
+                  for (int m = 0; m < 4; ++m) {
+                    const FT aym = m == 0   ? ayw[b][0]
+                                   : m == 1 ? ayw[b][1]
+                                   : m == 2 ? ayw[b][2]
+                                            : ayw[b][3];
+                    column_point<Q1, FT, WX, WY, WN>(A, s_f, wx0, wy0, X + rel, y0[b] + m, true,
+                                                     aym, wx, gby[b], Pj[b], ux, uy, inv_s, hc[b],
+                                                     acc_row[b]);
+                  }
+                }
               }
             }
-            // x rows of G_{B->n}, then the column's x weights (a5)
 #pragma unroll
-            for (int i = 0; i < Q1; ++i) {
-              FT v = FT(0);
+            for (int b = 0; b < JB; ++b)
 #pragma unroll
-              for (int ip = 0; ip < Q1; ++ip) v += gbx[i][ip] * hc[ip];
-              acc_row[i] += wx[i] * v;
-            }
+              for (int i = 0; i < Q1; ++i) {
+                FT v = FT(0);
+#pragma unroll
+                for (int ip = 0; ip < Q1; ++ip) v += gbx[i][ip] * hc[b][ip];
+                acc_row[b][i] += wx[i] * v;
+              }
           }
 #pragma unroll
-          for (int i = 0; i < Q1; ++i)
+          for (int b = 0; b < JB; ++b)
 #pragma unroll
-            for (int jj = 0; jj < Q1; ++jj)
-              if (jj == j) ft[i * Q1 + jj] = acc_row[i];
+            for (int i = 0; i < Q1; ++i)
+#pragma unroll
+              for (int jj = 0; jj < Q1; ++jj)
+                if (jj == j0 + b) ft[i * Q1 + jj] = acc_row[b][i];
         }
 
         // a6: moments in the peculiar frame of lambda_n (compensated sums).
