@@ -234,32 +234,41 @@ __device__ __forceinline__ void column_point(const StepArgs& A, const FT* s_f, i
   }
 }
 
-// a4 + a5 on the LDS window for the four rows of one stencil column, the
-// lane's whole column inside the window (node index k of its first row): the
-// y contractions with the G_{B->n} row gby, weighted by ayw and summed into
-// hc.  The second base of the reads is opaque to the optimiser, so that every
-// read takes its group and row from the instruction offset.  In FP64 each
-// row's reads are kept with their row: left free, the scheduler hoists the
-// reads of all four rows and holds them at once, which measured slower; FP32
-// gains from it.
-template <int Q1, class FT, int WX, int WN>
-__device__ __forceinline__ void window_column(const FT* s_f, int k, const FT* ayw, const FT* gby,
-                                              FT* hc) {
+// a4 + a5 on the LDS window for the four rows of one stencil column and JB y
+// speeds, the lane's whole column inside the window for each (node index
+// k[b] of speed b's first row): the y contractions with the G_{B->n} rows
+// gby[b], weighted by ayw[b] and summed into hc[b].  Row m of every speed is
+// taken before row m + 1 (the speeds' rows are independent, so their reads
+// are in flight together).  The second base of the reads is opaque to the
+// optimiser, so that every read takes its group and row from the instruction
+// offset.  In FP64 a scheduling barrier keeps each row's reads with the row:
+// left free, the scheduler hoists the reads of all four rows and holds them
+// at once, which measured slower; FP32 gains from it.
+template <int Q1, int JB, class FT, int WX, int WN>
+__device__ __forceinline__ void window_columns(const FT* s_f, const int* k, const FT (*ayw)[4],
+                                               const FT (*gby)[Q1], FT (*hc)[Q1]) {
   using W = Win<Q1, FT, WN>;
   constexpr int Q = Q1 * Q1;
-  const int e = k * W::G;
-  int eh = e + W::NGH * W::GS;
-  asm volatile("" : "+v"(eh));
+  int e[JB], eh[JB];
+#pragma unroll
+  for (int b = 0; b < JB; ++b) {
+    e[b] = k[b] * W::G;
+    eh[b] = e[b] + W::NGH * W::GS;
+    asm volatile("" : "+v"(eh[b]));
+  }
 #pragma unroll
   for (int m = 0; m < 4; ++m) {
-    FT f[Q];
-    W::load(s_f, e + m * WX * W::G, eh + m * WX * W::G, f);
 #pragma unroll
-    for (int ip = 0; ip < Q1; ++ip) {
-      FT v = FT(0);
+    for (int b = 0; b < JB; ++b) {
+      FT f[Q];
+      W::load(s_f, e[b] + m * WX * W::G, eh[b] + m * WX * W::G, f);
 #pragma unroll
-      for (int jp = 0; jp < Q1; ++jp) v += gby[jp] * f[ip * Q1 + jp];
-      hc[ip] += ayw[m] * v;
+      for (int ip = 0; ip < Q1; ++ip) {
+        FT v = FT(0);
+#pragma unroll
+        for (int jp = 0; jp < Q1; ++jp) v += gby[b][jp] * f[ip * Q1 + jp];
+        hc[b][ip] += ayw[b][m] * v;
+      }
     }
     if constexpr (sizeof(FT) == 8) {
       if (m < 3) __builtin_amdgcn_sched_barrier(0);
@@ -794,15 +803,17 @@ k_step(StepArgs A) {
             const int lx = X + rel - wx0;
             const bool col_in = (unsigned)lx < (unsigned)WX;
             if (need && all_in && col_in) {
+              int kk[JB];
 #pragma unroll
-              for (int b = 0; b < JB; ++b)
-                window_column<Q1, FT, WX, WN>(s_f, ly0[b] * WX + lx, ayw[b], gby[b], hc[b]);
+              for (int b = 0; b < JB; ++b) kk[b] = ly0[b] * WX + lx;
+              window_columns<Q1, JB, FT, WX, WN>(s_f, kk, ayw, gby, hc);
             } else if (need) {
 #pragma unroll
               for (int b = 0; b < JB; ++b) {
                 // with one speed per walk this path means the column leaves the window
                 if (JB > 1 && rows_in[b] && col_in) {
-                  window_column<Q1, FT, WX, WN>(s_f, ly0[b] * WX + lx, ayw[b], gby[b], hc[b]);
+                  const int kk = ly0[b] * WX + lx;
+                  window_columns<Q1, 1, FT, WX, WN>(s_f, &kk, &ayw[b], &gby[b], &hc[b]);
                 } else {
 #pragma unroll 1
                   for (int m = 0; m < 4; ++m) {
