@@ -526,7 +526,7 @@ __device__ void order_tiles(const uint16_t* keys, unsigned* order, unsigned ntil
 }
 
 template <int Q1, class FT, int TX, int TY, int H>
-__global__ void __launch_bounds__(TX * TY, sizeof(FT) == 8 ? 2 : 3)
+__global__ void __launch_bounds__(TX * TY, 2)
 k_step(StepArgs A) {
   constexpr int Q = Q1 * Q1;
   using L = Lat<Q1>;
@@ -747,10 +747,10 @@ k_step(StepArgs A) {
         // speeds (each with its own weight, zero where the column is outside
         // that speed's stencil).
         if (!wave_column_range(lo, hi, has, lo, hi)) hi = lo - 1;
-        // y speeds per column walk: FP64 takes two (the column's weights,
-        // tests and addresses serve both; measured faster), FP32 one (the
-        // extra registers cost it more than it saves)
-        constexpr int JB = (sizeof(FT) == 8 && Q1 % 2 == 0) ? 2 : 1;
+        // y speeds per column walk: two (the column's weights, tests and
+        // addresses serve both, and their rows are read interleaved; measured
+        // faster than one or four), one for D2Q9's three speeds
+        constexpr int JB = Q1 % 2 == 0 ? 2 : 1;
 #pragma unroll 1
         for (int j0 = 0; j0 < Q1; j0 += JB) {
           FT ayw[JB][4];
@@ -1030,9 +1030,9 @@ k_step(StepArgs A) {
 // Tile shapes (TX x TY nodes per block, halo H).  FP64: 32 x 16 nodes, for
 // D2Q16 a 42 x 26 window of 140 KiB of LDS (one block of 8 waves per CU, 2
 // waves per SIMD).  FP32-mixed: 32 x 8 nodes, a 42 x 18 window of 48 KiB,
-// three blocks of 4 waves per CU (registers capped at 168 per lane for 3
-// waves per SIMD; measured 7 % faster than 32 x 16 blocks at 2 waves per
-// SIMD, the spills included).
+// two blocks of 4 waves per CU (2 waves per SIMD; smaller tiles balance the
+// passes better than 32 x 16, and 3 waves per SIMD with registers capped at
+// 168 measured slower once two y speeds share a column walk).
 template <int Q1, class FT>
 struct StepTile {
   static constexpr int TX = 32, TY = sizeof(FT) == 8 ? 16 : 8, H = Q1 == 4 ? 5 : 4;
