@@ -55,9 +55,9 @@ def source_digest():
     return hashlib.sha256(open(STEP_SOURCE, "rb").read()).hexdigest()[:16]
 
 
-def make_cfg(w, precision):
+def make_cfg(w, precision, q1d=4):
     ny, nx = w.shape
-    cfg = pond.PondConfig(nx=nx, ny=ny, q1d=4, precision=precision, isothermal=w.isothermal,
+    cfg = pond.PondConfig(nx=nx, ny=ny, q1d=q1d, precision=precision, isothermal=w.isothermal,
                           bc_x=w.bc_x, bc_y=w.bc_y, tau=w.tau, max_iter=20)
     if precision == pond.POND_F32_MIXED:
         cfg = cfg.replace(eps_abs=1e-6, eps_rel=1e-5)
@@ -223,6 +223,28 @@ def riemann_2048(steps=200, warmup=2):
                      "ms_per_step": ms / steps}
     out["speedup_fp32_vs_fp64"] = out["f32_mixed"]["value"] / out["f64"]["value"]
     out["steps"] = steps
+    return out
+
+
+def riemann_d2q9(size=1024, steps=200, warmup=2):
+    """The paper's own lattice: the same Riemann flow on D2Q9 (temperatures
+    scaled to T_L = 1/3, same Mach numbers), both precisions, first steps."""
+    w = workloads.riemann2d(size, seed=3, T_scale=workloads.TL_D2Q9)
+    nodes = size * size
+    out, ends = {}, {}
+    for name, prec in (("f64", pond.POND_F64), ("f32_mixed", pond.POND_F32_MIXED)):
+        cfg = make_cfg(w, prec, q1d=3)
+        ms, a, _ = timed_steps(cfg, w, steps, warmup)
+        nxt, st = pond.step(cfg, a.clone(), stats=True)
+        ends[name] = (cfg, a)
+        out[name] = {"value": nodes * steps / (ms * 1e-3) / 1e6, "unit": "MLUPS",
+                     "ms_per_step": ms / steps, "mean_pc_passes_at_end": st["mean_iters"]}
+    out["speedup_fp32_vs_fp64"] = out["f32_mixed"]["value"] / out["f64"]["value"]
+    out["fp32_error_vs_fp64_at_end"] = field_errors(ends["f64"][0], ends["f64"][1],
+                                                    ends["f32_mixed"][0], ends["f32_mixed"][1])
+    out["steps"] = steps
+    out["workload"] = (f"riemann2d on D2Q9, {size}x{size}, temperatures x 1/3 (T_L = 1/3), "
+                       "tau 0.55, zero-gradient edges, seed 3, adaptive")
     return out
 
 
@@ -403,6 +425,8 @@ def main():
         fp32["error_vs_fp64_other_configs"] = fp32_error_other_configs()
         result["fp32_mixed"] = fp32
         result["riemann2d_2048"] = riemann_2048()
+        log("[bench] D2Q9 Riemann 1024^2")
+        result["d2q9_riemann2d_1024"] = riemann_d2q9()
 
     if not args.no_adjoint:
         log("[bench] adjoint / forward")

@@ -124,12 +124,16 @@ def compressible_taylor_green(N: int = 128, mach: float = 0.5, T0: float = 1.0, 
                     tau, 0, 0, 0, steps, {"u0": u0, "k": k, "seed": seed})
 
 
-def riemann2d(N: int = 1024, seed: int = 3, tau: float = 0.55, steps: int = 2000) -> Workload:
+def riemann2d(N: int = 1024, seed: int = 3, tau: float = 0.55, steps: int = 2000,
+              T_scale: float = 1.0) -> Workload:
+    """Four-quadrant 2-D Riemann problem.  T_scale multiplies every temperature
+    (velocities follow through sqrt(T), so the Mach numbers stay): 1 for D2Q16
+    (T_L = 1), TL_D2Q9 for the same flow on D2Q9."""
     rng = np.random.default_rng(seed)
     # quadrant order: (lower-left, lower-right, upper-left, upper-right) in (y, x)
     q_rho = rng.uniform(0.5, 1.5, 4)
     q_p = rng.uniform(0.3, 1.5, 4)
-    q_T = q_p / q_rho
+    q_T = q_p / q_rho * T_scale
     q_ux = rng.uniform(-0.8, 0.8, 4) * np.sqrt(q_T)
     q_uy = rng.uniform(-0.8, 0.8, 4) * np.sqrt(q_T)
     h = N // 2
@@ -139,7 +143,7 @@ def riemann2d(N: int = 1024, seed: int = 3, tau: float = 0.55, steps: int = 2000
     quad[h:, h:] = 3
     return Workload("riemann2d", q_rho[quad], q_ux[quad], q_uy[quad], q_T[quad], tau, 0, 1, 1,
                     steps, {"seed": seed, "rho": q_rho.tolist(), "p": q_p.tolist(),
-                            "ux": q_ux.tolist(), "uy": q_uy.tolist()})
+                            "ux": q_ux.tolist(), "uy": q_uy.tolist(), "T_scale": T_scale})
 
 
 def uniform(nx: int, ny: int, rho: float = 1.0, ux: float = 0.0, uy: float = 0.0, T: float = 1.0,
