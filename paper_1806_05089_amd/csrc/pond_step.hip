@@ -747,10 +747,10 @@ k_step(StepArgs A) {
         // speeds (each with its own weight, zero where the column is outside
         // that speed's stencil).
         if (!wave_column_range(lo, hi, has, lo, hi)) hi = lo - 1;
-        // y speeds per column walk: two (the column's weights, tests and
-        // addresses serve both, and their rows are read interleaved; measured
-        // faster than one or four), one for D2Q9's three speeds
-        constexpr int JB = Q1 % 2 == 0 ? 2 : 1;
+        // y speeds per column walk (the column's weights, tests and addresses
+        // serve them all, and their rows are read interleaved): D2Q16 two
+        // (measured faster than one or four), D2Q9 all three
+        constexpr int JB = Q1 % 2 == 0 ? 2 : 3;
 #pragma unroll 1
         for (int j0 = 0; j0 < Q1; j0 += JB) {
           FT ayw[JB][4];
