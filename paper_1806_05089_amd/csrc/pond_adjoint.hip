@@ -21,6 +21,7 @@
 #include <hip/hip_runtime.h>
 #include <limits.h>
 #include <math.h>
+#include <stdlib.h>
 
 #include "pond_device.hpp"
 #include "pond_internal.hpp"
@@ -90,13 +91,16 @@ struct Gauge {
   double ux, uy, s, T;
 };
 
-template <int Q1, class FT, int TX, int TY, int H>
+// Tile of TX x TY nodes with YS lanes per node (YS = 2: the two lanes of a
+// node take half of the y speeds each).
+template <int Q1, class FT, int TX, int TY, int H, int YS>
 struct AdjShape {
   static constexpr int WX = TX + 2 * H;
   static constexpr int WY = TY + 2 * H;
   static constexpr int WN = WX * WY;
-  static constexpr int NT = TX * TY;
+  static constexpr int NT = TX * TY * YS;  // threads
   static constexpr int NW = NT / 64;
+  static_assert(YS == 1 || Q1 % YS == 0, "the y speeds split evenly over a node's lanes");
   static_assert(((size_t)Win<Q1, double, WN>::size + (size_t)Q1 * Q1 * WN) * sizeof(double) + 1024 <=
                     160 * 1024,
                 "LDS");
@@ -414,14 +418,15 @@ __device__ __forceinline__ void adj_hbm_point(const Lane<Q1, FT, WX, WY, WN>& c,
       atomicAdd(&A.af_in[(size_t)(ip * Q1 + jp) * c.plane + src], Ux[ip] * gyr[jp]);
 }
 
-// Adjoint of one forward pass at gauge G with cotangent Fb of its output.
-// Scatters the collocation points' cotangents and adds the cotangent of the
-// gauge (u_x, u_y, s) to (gux, guy, gs).  Column by column like the forward
+// Adjoint of one forward pass at gauge G with cotangent Fb of its output, for
+// the y speeds jlo .. jhi - 1 (all of them, or the lane's half when two lanes
+// share a node).  Scatters the collocation points' cotangents and adds the
+// cotangent of the gauge (u_x, u_y, s) to (gux, guy, gs).  Column by column like the forward
 // pass: at each collocation point the cotangents of the four x speeds are
 // summed before they are scattered (one LDS atomic per population).
 template <int Q1, class FT, int WX, int WY, int WN>
 __device__ void adjoint_pass(const Lane<Q1, FT, WX, WY, WN>& c, const Gauge& G, const double* Fb,
-                             double& gux, double& guy, double& gs) {
+                             int jlo, int jhi, double& gux, double& guy, double& gs) {
   using L = Lat<Q1>;
   using W = Win<Q1, double, WN>;
   constexpr int QH = Q1 * Q1 / 2;
@@ -437,7 +442,7 @@ __device__ void adjoint_pass(const Lane<Q1, FT, WX, WY, WN>& c, const Gauge& G, 
     for (int ip = 0; ip < Q1; ++ip) gbx_bar[i][ip] = 0.0;
   }
 #pragma unroll 1
-  for (int j = 0; j < Q1; ++j) {
+  for (int j = jlo; j < jhi; ++j) {
     const double cj = speed_rt<Q1>(j);
     const double yd = double(c.Y) - (G.s * cj + G.uy);
     const double fly = floor(yd);
@@ -544,12 +549,12 @@ __device__ void adjoint_pass(const Lane<Q1, FT, WX, WY, WN>& c, const Gauge& G, 
   gs -= zz * inv_s;
 }
 
-template <int Q1, class FT, int TX, int TY, int H>
-__global__ void __launch_bounds__(TX * TY)
+template <int Q1, class FT, int TX, int TY, int H, int YS>
+__global__ void __launch_bounds__(TX * TY * YS)
 k_step_adjoint(AdjArgs A) {
   constexpr int Q = Q1 * Q1;
   using L = Lat<Q1>;
-  using S = AdjShape<Q1, FT, TX, TY, H>;
+  using S = AdjShape<Q1, FT, TX, TY, H, YS>;
   constexpr int WX = S::WX, WY = S::WY, WN = S::WN, NT = S::NT;
   __shared__ __align__(16) double s_fB[Win<Q1, double, WN>::size];
   __shared__ double s_acc[Q * WN];
@@ -574,8 +579,11 @@ k_step_adjoint(AdjArgs A) {
     int tl = tid;
     asm volatile("" : "+v"(tl));  // keep per-lane values from being hoisted out of the loop
     const int wave = tl >> 6, lane = tl & 63;
-    const int X = bx0 + (wave % (TX / 8)) * 8 + (lane & 7);
-    const int Y = by0 + (wave / (TX / 8)) * 8 + (lane >> 3);
+    // YS = 1: 8 x 8 nodes per wave; YS = 2: lanes 2n, 2n + 1 share a node,
+    // a wave holds two rows of 16 nodes
+    const int half = YS == 2 ? (tl & 1) : 0;
+    const int X = YS == 2 ? bx0 + (tl >> 1) % TX : bx0 + (wave % (TX / 8)) * 8 + (lane & 7);
+    const int Y = YS == 2 ? by0 + (tl >> 1) / TX : by0 + (wave / (TX / 8)) * 8 + (lane >> 3);
     const size_t plane = (size_t)A.nx * A.ny;
     const size_t node = (size_t)Y * A.nx + X;
     const FT* __restrict__ fin = static_cast<const FT*>(A.f_in);
@@ -849,7 +857,21 @@ k_step_adjoint(AdjArgs A) {
           guy += guy_k;
           gs += gs_k;
         }
-        adjoint_pass<Q1, FT, WX, WY, WN>(c, G, Fb, gux, guy, gs);
+        {
+          // the lane's y speeds; with two lanes per node the pair sums its
+          // contributions to the gauge cotangent
+          double dgx = 0.0, dgy = 0.0, dgs = 0.0;
+          adjoint_pass<Q1, FT, WX, WY, WN>(c, G, Fb, half * (Q1 / YS), (half + 1) * (Q1 / YS), dgx,
+                                           dgy, dgs);
+          if constexpr (YS == 2) {
+            dgx += __shfl_xor(dgx, 1);
+            dgy += __shfl_xor(dgy, 1);
+            dgs += __shfl_xor(dgs, 1);
+          }
+          gux += dgx;
+          guy += dgy;
+          gs += dgs;
+        }
         gT += gs * L::inv_TL / (2.0 * G.s);
         gux_1 = gux;
         guy_1 = guy;
@@ -870,9 +892,11 @@ k_step_adjoint(AdjArgs A) {
       } else {
         sT = A.isothermal ? gT_1 : 0.0;
       }
-      atomicAdd(&A.ag_in[node], sux);
-      atomicAdd(&A.ag_in[plane + node], suy);
-      atomicAdd(&A.ag_in[2 * plane + node], sT);
+      if (half == 0) {  // once per node
+        atomicAdd(&A.ag_in[node], sux);
+        atomicAdd(&A.ag_in[plane + node], suy);
+        atomicAdd(&A.ag_in[2 * plane + node], sT);
+      }
     }
 
     __syncthreads();
@@ -958,7 +982,8 @@ k_step_adjoint(AdjArgs A) {
     __syncthreads();  // LDS of this tile is free
   }  // tile loop
 
-  // d/dtau of the block's tiles
+  // d/dtau of the block's tiles (every lane of a node holds it)
+  if (YS == 2 && (tid & 1)) tau_bar = 0.0;
   if (A.adj_tau) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) tau_bar += __shfl_xor(tau_bar, off);
@@ -979,12 +1004,14 @@ __global__ void k_zero_f64(double* p, size_t n) {
   if (i < n) p[i] = 0.0;
 }
 
-// Adjoint tile: 16 x 16 nodes, halo 4 (24 x 24 window, two FP64 planes sets:
-// 144 KiB of LDS, one block per CU).  Persistent grid: one block per resident
-// slot, at most one per tile.
-template <int Q1, class FT>
-hipError_t launch_adjoint_t(const AdjArgs& a, hipStream_t s) {
-  constexpr int TX = 16, TY = 16, H = 4;
+// Adjoint tiles, halo 4.  YS = 1: 16 x 16 nodes, one lane each (24 x 24
+// window, two FP64 plane sets: 144 KiB of LDS, one block per CU).  YS = 2:
+// 16 x 8 nodes, two lanes each (24 x 16 window, 96 KiB): half the work per
+// lane, for grids too small to fill the device with one lane per node.
+// Persistent grid: one block per resident slot, at most one per tile.
+template <int Q1, class FT, int YS>
+hipError_t launch_adjoint_ys(const AdjArgs& a, hipStream_t s) {
+  constexpr int TX = 16, TY = YS == 2 ? 8 : 16, H = 4;
   constexpr int kMaxDev = 64;
   static int resident[kMaxDev] = {0};
   int dev = 0;
@@ -996,14 +1023,37 @@ hipError_t launch_adjoint_t(const AdjArgs& a, hipStream_t s) {
     e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return e;
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &per_cu, reinterpret_cast<const void*>(&k_step_adjoint<Q1, FT, TX, TY, H>), TX * TY, 0);
+        &per_cu, reinterpret_cast<const void*>(&k_step_adjoint<Q1, FT, TX, TY, H, YS>),
+        TX * TY * YS, 0);
     if (e != hipSuccess) return e;
     resident[dev] = (cus > 0 ? cus : 1) * (per_cu > 0 ? per_cu : 1);
   }
   const long long tiles = (long long)((a.nx + TX - 1) / TX) * ((a.ny + TY - 1) / TY);
   const int nblk = (int)(tiles < resident[dev] ? tiles : resident[dev]);
-  hipLaunchKernelGGL((k_step_adjoint<Q1, FT, TX, TY, H>), dim3(nblk), dim3(TX * TY), 0, s, a);
+  hipLaunchKernelGGL((k_step_adjoint<Q1, FT, TX, TY, H, YS>), dim3(nblk), dim3(TX * TY * YS), 0,
+                     s, a);
   return hipGetLastError();
+}
+
+// Two lanes per node while the one-lane tiles would not give every CU two
+// (POND_ADJOINT_LANES = 1 or 2 forces the choice, for tests).
+template <int Q1, class FT>
+hipError_t launch_adjoint_t(const AdjArgs& a, hipStream_t s) {
+  if constexpr (Q1 % 2 == 0) {
+    const char* env = getenv("POND_ADJOINT_LANES");
+    const int forced = env ? atoi(env) : 0;
+    if (forced == 2) return launch_adjoint_ys<Q1, FT, 2>(a, s);
+    if (forced != 1) {
+      int dev = 0, cus = 0;
+      hipError_t e = hipGetDevice(&dev);
+      if (e == hipSuccess)
+        e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+      if (e != hipSuccess) return e;
+      const long long tiles1 = (long long)((a.nx + 15) / 16) * ((a.ny + 15) / 16);
+      if (tiles1 < 2LL * cus) return launch_adjoint_ys<Q1, FT, 2>(a, s);
+    }
+  }
+  return launch_adjoint_ys<Q1, FT, 1>(a, s);
 }
 
 }  // namespace

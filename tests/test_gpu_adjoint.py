@@ -5,7 +5,8 @@ gives exact directional derivatives of its computed map.  With the pass count
 fixed (fixed-iteration mode) the GPU adjoint differentiates the same map, so
   <J delta, w>  (oracle, complex step)  ==  <delta, J^T w>  (GPU adjoint)
 to round-off, for random directions delta and cotangents w, and element by
-element on a tiny grid.
+element on a tiny grid.  POND_ADJOINT_LANES selects the one-lane or the
+two-lane adjoint kernel (read at every call).
 """
 import numpy as np
 import pytest
@@ -68,9 +69,15 @@ CASES = [
 ]
 
 
+@pytest.mark.parametrize("lanes", [1, 2])
 @pytest.mark.parametrize("name,make,q,kw", CASES, ids=[c[0] for c in CASES])
-def test_dot_product_against_complex_step(gpu, name, make, q, kw):
-    print(f"case {name}", flush=True)
+def test_dot_product_against_complex_step(gpu, monkeypatch, name, make, q, kw, lanes):
+    """Both adjoint kernels: one lane per node (large grids) and two lanes per
+    node, each taking half of the y speeds (small grids; D2Q16 only)."""
+    if q == 3 and lanes == 2:
+        pytest.skip("D2Q9's three y speeds do not split over two lanes")
+    monkeypatch.setenv("POND_ADJOINT_LANES", str(lanes))
+    print(f"case {name} lanes {lanes}", flush=True)
     w = make()
     cfg, st, out = _setup(w, q=q, fixed_iter=3, **kw)
     f = st.f.double().cpu().numpy()
