@@ -91,8 +91,8 @@ struct Gauge {
   double ux, uy, s, T;
 };
 
-// Tile of TX x TY nodes with YS lanes per node (YS = 2: the two lanes of a
-// node take half of the y speeds each).
+// Tile of TX x TY nodes with YS lanes per node (YS = 2 or 4: the lanes of a
+// node take an equal share of the y speeds each).
 template <int Q1, class FT, int TX, int TY, int H, int YS>
 struct AdjShape {
   static constexpr int WX = TX + 2 * H;
@@ -100,7 +100,8 @@ struct AdjShape {
   static constexpr int WN = WX * WY;
   static constexpr int NT = TX * TY * YS;  // threads
   static constexpr int NW = NT / 64;
-  static_assert(YS == 1 || Q1 % YS == 0, "the y speeds split evenly over a node's lanes");
+  static_assert(YS == 1 || (Q1 % YS == 0 && (YS & (YS - 1)) == 0),
+                "the y speeds split evenly over a node's lanes, a power of two");
   static_assert(((size_t)Win<Q1, double, WN>::size + (size_t)Q1 * Q1 * WN) * sizeof(double) + 1024 <=
                     160 * 1024,
                 "LDS");
@@ -419,8 +420,8 @@ __device__ __forceinline__ void adj_hbm_point(const Lane<Q1, FT, WX, WY, WN>& c,
 }
 
 // Adjoint of one forward pass at gauge G with cotangent Fb of its output, for
-// the y speeds jlo .. jhi - 1 (all of them, or the lane's half when two lanes
-// share a node).  Scatters the collocation points' cotangents and adds the
+// the y speeds jlo .. jhi - 1 (all of them, or the lane's share when several
+// lanes share a node).  Scatters the collocation points' cotangents and adds the
 // cotangent of the gauge (u_x, u_y, s) to (gux, guy, gs).  Column by column like the forward
 // pass: at each collocation point the cotangents of the four x speeds are
 // summed before they are scattered (one LDS atomic per population).
@@ -579,11 +580,11 @@ k_step_adjoint(AdjArgs A) {
     int tl = tid;
     asm volatile("" : "+v"(tl));  // keep per-lane values from being hoisted out of the loop
     const int wave = tl >> 6, lane = tl & 63;
-    // YS = 1: 8 x 8 nodes per wave; YS = 2: lanes 2n, 2n + 1 share a node,
-    // a wave holds two rows of 16 nodes
-    const int half = YS == 2 ? (tl & 1) : 0;
-    const int X = YS == 2 ? bx0 + (tl >> 1) % TX : bx0 + (wave % (TX / 8)) * 8 + (lane & 7);
-    const int Y = YS == 2 ? by0 + (tl >> 1) / TX : by0 + (wave / (TX / 8)) * 8 + (lane >> 3);
+    // YS = 1: 8 x 8 nodes per wave; YS > 1: lanes YS n .. YS n + YS - 1
+    // share a node (part = which share of the y speeds), rows of 16 nodes
+    const int part = YS > 1 ? (tl & (YS - 1)) : 0;
+    const int X = YS > 1 ? bx0 + (tl / YS) % TX : bx0 + (wave % (TX / 8)) * 8 + (lane & 7);
+    const int Y = YS > 1 ? by0 + (tl / YS) / TX : by0 + (wave / (TX / 8)) * 8 + (lane >> 3);
     const size_t plane = (size_t)A.nx * A.ny;
     const size_t node = (size_t)Y * A.nx + X;
     const FT* __restrict__ fin = static_cast<const FT*>(A.f_in);
@@ -858,15 +859,16 @@ k_step_adjoint(AdjArgs A) {
           gs += gs_k;
         }
         {
-          // the lane's y speeds; with two lanes per node the pair sums its
-          // contributions to the gauge cotangent
+          // the lane's y speeds; the lanes of a node sum their contributions
+          // to the gauge cotangent
           double dgx = 0.0, dgy = 0.0, dgs = 0.0;
-          adjoint_pass<Q1, FT, WX, WY, WN>(c, G, Fb, half * (Q1 / YS), (half + 1) * (Q1 / YS), dgx,
+          adjoint_pass<Q1, FT, WX, WY, WN>(c, G, Fb, part * (Q1 / YS), (part + 1) * (Q1 / YS), dgx,
                                            dgy, dgs);
-          if constexpr (YS == 2) {
-            dgx += __shfl_xor(dgx, 1);
-            dgy += __shfl_xor(dgy, 1);
-            dgs += __shfl_xor(dgs, 1);
+#pragma unroll
+          for (int off = 1; off < YS; off <<= 1) {
+            dgx += __shfl_xor(dgx, off);
+            dgy += __shfl_xor(dgy, off);
+            dgs += __shfl_xor(dgs, off);
           }
           gux += dgx;
           guy += dgy;
@@ -892,7 +894,7 @@ k_step_adjoint(AdjArgs A) {
       } else {
         sT = A.isothermal ? gT_1 : 0.0;
       }
-      if (half == 0) {  // once per node
+      if (part == 0) {  // once per node
         atomicAdd(&A.ag_in[node], sux);
         atomicAdd(&A.ag_in[plane + node], suy);
         atomicAdd(&A.ag_in[2 * plane + node], sT);
@@ -983,7 +985,7 @@ k_step_adjoint(AdjArgs A) {
   }  // tile loop
 
   // d/dtau of the block's tiles (every lane of a node holds it)
-  if (YS == 2 && (tid & 1)) tau_bar = 0.0;
+  if (YS > 1 && (tid & (YS - 1))) tau_bar = 0.0;
   if (A.adj_tau) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) tau_bar += __shfl_xor(tau_bar, off);
@@ -1004,14 +1006,15 @@ __global__ void k_zero_f64(double* p, size_t n) {
   if (i < n) p[i] = 0.0;
 }
 
-// Adjoint tiles, halo 4.  YS = 1: 16 x 16 nodes, one lane each (24 x 24
-// window, two FP64 plane sets: 144 KiB of LDS, one block per CU).  YS = 2:
-// 16 x 8 nodes, two lanes each (24 x 16 window, 96 KiB): half the work per
-// lane, for grids too small to fill the device with one lane per node.
+// Adjoint tiles, halo 4, 256 threads.  YS = 1: 16 x 16 nodes, one lane each
+// (24 x 24 window, two FP64 plane sets: 144 KiB of LDS, one block per CU).
+// YS = 2: 16 x 8 nodes, two lanes each (24 x 16 window, 96 KiB); YS = 4:
+// 16 x 4 nodes, four lanes each (24 x 12 window): less serial work per lane,
+// for grids too small to fill the device with one lane per node.
 // Persistent grid: one block per resident slot, at most one per tile.
 template <int Q1, class FT, int YS>
 hipError_t launch_adjoint_ys(const AdjArgs& a, hipStream_t s) {
-  constexpr int TX = 16, TY = YS == 2 ? 8 : 16, H = 4;
+  constexpr int TX = 16, TY = 16 / YS, H = 4;
   constexpr int kMaxDev = 64;
   static int resident[kMaxDev] = {0};
   int dev = 0;
@@ -1035,14 +1038,16 @@ hipError_t launch_adjoint_ys(const AdjArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-// Two lanes per node while the one-lane tiles would not give every CU two
-// (POND_ADJOINT_LANES = 1 or 2 forces the choice, for tests).
+// Lanes per node from the grid: four while the one-lane tiles would not give
+// every other CU one, two while they would not give every CU two
+// (POND_ADJOINT_LANES = 1, 2 or 4 forces the choice, for tests).
 template <int Q1, class FT>
 hipError_t launch_adjoint_t(const AdjArgs& a, hipStream_t s) {
   if constexpr (Q1 % 2 == 0) {
     const char* env = getenv("POND_ADJOINT_LANES");
     const int forced = env ? atoi(env) : 0;
     if (forced == 2) return launch_adjoint_ys<Q1, FT, 2>(a, s);
+    if (forced == 4) return launch_adjoint_ys<Q1, FT, 4>(a, s);
     if (forced != 1) {
       int dev = 0, cus = 0;
       hipError_t e = hipGetDevice(&dev);
@@ -1050,6 +1055,7 @@ hipError_t launch_adjoint_t(const AdjArgs& a, hipStream_t s) {
         e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
       if (e != hipSuccess) return e;
       const long long tiles1 = (long long)((a.nx + 15) / 16) * ((a.ny + 15) / 16);
+      if (2 * tiles1 < cus) return launch_adjoint_ys<Q1, FT, 4>(a, s);
       if (tiles1 < 2LL * cus) return launch_adjoint_ys<Q1, FT, 2>(a, s);
     }
   }

@@ -6,7 +6,7 @@ fixed (fixed-iteration mode) the GPU adjoint differentiates the same map, so
   <J delta, w>  (oracle, complex step)  ==  <delta, J^T w>  (GPU adjoint)
 to round-off, for random directions delta and cotangents w, and element by
 element on a tiny grid.  POND_ADJOINT_LANES selects the one-lane or the
-two-lane adjoint kernel (read at every call).
+two- or four-lane adjoint kernel (read at every call).
 """
 import numpy as np
 import pytest
@@ -69,13 +69,14 @@ CASES = [
 ]
 
 
-@pytest.mark.parametrize("lanes", [1, 2])
+@pytest.mark.parametrize("lanes", [1, 2, 4])
 @pytest.mark.parametrize("name,make,q,kw", CASES, ids=[c[0] for c in CASES])
 def test_dot_product_against_complex_step(gpu, monkeypatch, name, make, q, kw, lanes):
-    """Both adjoint kernels: one lane per node (large grids) and two lanes per
-    node, each taking half of the y speeds (small grids; D2Q16 only)."""
-    if q == 3 and lanes == 2:
-        pytest.skip("D2Q9's three y speeds do not split over two lanes")
+    """Every adjoint kernel: one lane per node (large grids) and two or four
+    lanes per node, each taking a share of the y speeds (smaller grids; D2Q16
+    only)."""
+    if q == 3 and lanes > 1:
+        pytest.skip("D2Q9's three y speeds do not split over several lanes")
     monkeypatch.setenv("POND_ADJOINT_LANES", str(lanes))
     print(f"case {name} lanes {lanes}", flush=True)
     w = make()
