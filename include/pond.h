@@ -149,6 +149,36 @@ int pond_step_adjoint(const pond_config* cfg, const pond_state* in, const pond_s
                       const pond_state* adj_out, pond_state* adj_in, double* adj_tau,
                       void* hip_stream);
 
+/*
+ * Recorded steps, for callers that run the step themselves before the adjoint
+ * (a checkpointed rollout replays each segment anyway): pond_step_record is
+ * one pond_step (nsteps = 1, same arithmetic, same out) that also writes the
+ * pass history the adjoint needs -- every node's seed gauge, the gauge and
+ * density after each predictor-corrector pass (eqs. (10)-(16)) and the
+ * populations of its last pass -- to `tape`; pond_step_adjoint_recorded is
+ * pond_step_adjoint about that step, reading the tape instead of running the
+ * step again.
+ *
+ * pond_tape_bytes: the tape's size for cfg, written to *bytes (host pointer):
+ *   ((K + 1) * 4 + q1d^2) * nx * ny * 8 bytes, K = fixed_iter, or max_iter in
+ *   adaptive mode.
+ * pond_step_record: tape (device, caller-owned, pond_tape_bytes bytes) must
+ *   not overlap the states; out->iters is required.  POND_E_ALIAS / _NULL as
+ *   for pond_step.
+ * pond_step_adjoint_recorded: `tape` and out_fwd->iters as written by
+ *   pond_step_record(cfg, in, out_fwd, tape) with the same cfg; a tape of
+ *   another step gives a meaningless result (nodes whose pass count does not
+ *   fit the tape carry no derivative; nothing is read outside it).  Other
+ *   arguments as for pond_step_adjoint; adj_in must not overlap the tape.
+ */
+int pond_tape_bytes(const pond_config* cfg, int64_t* bytes);
+int pond_step_record(const pond_config* cfg, const pond_state* in, pond_state* out, void* tape,
+                     void* hip_stream);
+int pond_step_adjoint_recorded(const pond_config* cfg, const pond_state* in,
+                               const pond_state* out_fwd, const void* tape,
+                               const pond_state* adj_out, pond_state* adj_in, double* adj_tau,
+                               void* hip_stream);
+
 /* Message for the last nonzero return on this thread ("" if none). */
 const char* pond_last_error(void);
 

@@ -25,7 +25,8 @@ POND_ITERS_NONCONVERGED = 0x40
 POND_ITERS_BAD = 0x80
 
 EXPORTED = ("pond_init", "pond_step", "pond_moments", "pond_step_adjoint", "pond_last_error",
-            "pond_abi_version")
+            "pond_abi_version", "pond_tape_bytes", "pond_step_record",
+            "pond_step_adjoint_recorded")
 
 
 class pond_config(C.Structure):
@@ -77,6 +78,12 @@ def load(path: str | None = None):
     lib.pond_moments.restype = C.c_int
     lib.pond_step_adjoint.argtypes = [cp, sp, sp, sp, sp, dp, dp]
     lib.pond_step_adjoint.restype = C.c_int
+    lib.pond_tape_bytes.argtypes = [cp, C.POINTER(C.c_int64)]
+    lib.pond_tape_bytes.restype = C.c_int
+    lib.pond_step_record.argtypes = [cp, sp, sp, dp, dp]
+    lib.pond_step_record.restype = C.c_int
+    lib.pond_step_adjoint_recorded.argtypes = [cp, sp, sp, dp, sp, sp, dp, dp]
+    lib.pond_step_adjoint_recorded.restype = C.c_int
     lib.pond_last_error.argtypes = []
     lib.pond_last_error.restype = C.c_char_p
     lib.pond_abi_version.argtypes = []

@@ -3,8 +3,9 @@
 ``PondRollout.apply(f0, g0, tau, cfg, nsteps, checkpoint_every)`` runs
 ``nsteps`` pond_step launches and returns the final (f, g).  Its backward pass
 replays each segment of ``checkpoint_every`` steps from the saved state at the
-segment start (so memory holds nsteps / K checkpoints plus one segment) and
-calls ``pond_step_adjoint`` step by step in reverse.  Gradients flow to the
+segment start with ``pond_step_record`` (so memory holds nsteps / K checkpoints
+plus one segment's states and pass histories) and calls
+``pond_step_adjoint_recorded`` step by step in reverse.  Gradients flow to the
 initial populations and gauge and to tau (nu = T_ref (tau - 1/2) dt, so
 dJ/dnu = (dJ/dtau) / T_ref).
 
@@ -83,14 +84,18 @@ class PondRollout(torch.autograd.Function):
         atau = torch.zeros(1, dtype=torch.float64, device=dev)
         for k0, f_ck, g_ck in reversed(ctx.checkpoints):
             k1 = min(k0 + ctx.K, ctx.nsteps)
-            # replay the segment, keeping every state and its pass counts
+            # replay the segment, keeping every state and the pass history each
+            # step records, then run the recorded steps' adjoints backwards
             states = [PondState(f_ck.clone(), g_ck.clone(),
                                 torch.zeros((cfg.ny, cfg.nx), dtype=torch.uint8, device=dev))]
+            tapes = []
             for _ in range(k0, k1):
-                out, _ = pond.step(cfg, states[-1])
+                out, tape = pond.step_record(cfg, states[-1])
                 states.append(out)
+                tapes.append(tape)
             for k in range(k1 - k0, 0, -1):
-                af, ag = pond.step_adjoint(cfg, states[k - 1], states[k], af, ag, atau)
+                af, ag = pond.step_adjoint_recorded(cfg, states[k - 1], states[k], tapes.pop(),
+                                                    af, ag, atau)
         return af.to(ctx.checkpoints[0][1].dtype) if cfg.precision == pond.POND_F32_MIXED else af, \
             ag, atau.reshape(()), None, None, None
 

@@ -39,6 +39,7 @@ struct AdjArgs {
   const uint8_t* iters;
   const double* tape;    // pass history of the step (layout of StepArgs::tape)
   const double* tape_f;  // last pass's populations of the step
+  int tape_slots;        // gauge slots per node in the tape
   const double* af_out;  // [Q][N]
   const double* ag_out;  // [3][N]
   double* af_in;         // [Q][N], zeroed before the launch
@@ -596,7 +597,7 @@ k_step_adjoint(AdjArgs A) {
       const unsigned it = A.iters[node];
       K = it & POND_ITERS_MASK;
       // nodes the forward step flagged bad carry no derivative
-      if ((it & POND_ITERS_BAD) || K < 1 || K >= kMaxPasses) active = false;
+      if ((it & POND_ITERS_BAD) || K < 1 || K >= kMaxPasses || K >= A.tape_slots) active = false;
     }
 
     // seed (eqs. 7-8) and the modes of the seed-independence experiment
@@ -1066,7 +1067,7 @@ hipError_t launch_adjoint_t(const AdjArgs& a, hipStream_t s) {
 
 hipError_t launch_adjoint(const pond_config& c, const void* f_in, const double* g_in,
                           const uint8_t* iters, const double* tape, const double* tape_f,
-                          const double* adj_f_out, const double* adj_g_out,
+                          int tape_slots, const double* adj_f_out, const double* adj_g_out,
                           double* adj_f_in, double* adj_g_in, double* adj_tau, TileQueue* queue,
                           hipStream_t s) {
   const size_t plane = (size_t)c.nx * c.ny;
@@ -1088,6 +1089,7 @@ hipError_t launch_adjoint(const pond_config& c, const void* f_in, const double* 
   a.iters = iters;
   a.tape = tape;
   a.tape_f = tape_f;
+  a.tape_slots = tape_slots;
   a.af_out = adj_f_out;
   a.ag_out = adj_g_out;
   a.af_in = adj_f_in;

@@ -210,6 +210,66 @@ hipError_t launch_step_on(const pond_config& c, Slot* slot, pond::StepArgs& a, h
   return hipSuccess;
 }
 
+// Pass history of one step (layout of StepArgs::tape / tape_f, one block):
+// (kslots * 4 + Q) * N doubles, kslots = 1 + the most passes a node can take.
+struct TapeLayout {
+  int kslots;
+  size_t tape_f_offset;  // bytes
+  size_t total;          // bytes
+};
+TapeLayout tape_layout(const pond_config& c) {
+  TapeLayout t;
+  const size_t plane = (size_t)c.nx * c.ny;
+  t.kslots = 1 + (c.fixed_iter > 0 ? c.fixed_iter : c.max_iter);
+  t.tape_f_offset = (size_t)t.kslots * 4 * plane * sizeof(double);
+  t.total = t.tape_f_offset + (size_t)c.q1d * c.q1d * plane * sizeof(double);
+  return t;
+}
+
+// One step from (in_f, in_g) with its pass history written to `tape`.
+hipError_t record_step(const pond_config& c, Slot* slot, const void* in_f, const double* in_g,
+                       void* out_f, double* out_g, uint8_t* out_iters, char* tape,
+                       hipStream_t s) {
+  pond::StepArgs a = step_args(c, slot);
+  a.f_in = in_f;
+  a.g_in = in_g;
+  a.f_out = out_f;
+  a.g_out = out_g;
+  a.iters = out_iters;
+  a.tape = reinterpret_cast<double*>(tape);
+  a.tape_f = reinterpret_cast<double*>(tape + tape_layout(c).tape_f_offset);
+  return launch_step_on(c, slot, a, s);
+}
+
+// adj_in must not overlap the adjoint's inputs (nor the tape, if given).
+int check_adjoint_aliasing(const pond_config& c, const pond_state* in, const pond_state* adj_out,
+                           const pond_state* adj_in, const void* tape) {
+  const size_t plane = (size_t)c.nx * c.ny;
+  const size_t afb = plane * c.q1d * c.q1d * sizeof(double), agb = g_bytes(c);
+  const size_t fb = f_bytes(c), tb = tape_layout(c).total;
+  if (overlap(adj_in->f, afb, adj_out->f, afb) || overlap(adj_in->g, agb, adj_out->g, agb) ||
+      overlap(adj_in->f, afb, in->f, fb) || overlap(adj_in->g, agb, in->g, agb) ||
+      overlap(adj_in->f, afb, adj_in->g, agb) ||
+      (tape && (overlap(adj_in->f, afb, tape, tb) || overlap(adj_in->g, agb, tape, tb))))
+    return fail(POND_E_ALIAS, "pond_step_adjoint: adj_in overlaps another buffer");
+  return POND_OK;
+}
+
+// The adjoint kernel on a recorded step (pass counts `iters`, history `tape`).
+int launch_adjoint_on(const pond_config& c, Slot* slot, const pond_state* in,
+                      const uint8_t* iters, const char* tape, const pond_state* adj_out,
+                      pond_state* adj_in, double* adj_tau, hipStream_t s) {
+  const TapeLayout t = tape_layout(c);
+  const hipError_t e = pond::launch_adjoint(
+      c, in->f, in->g, iters, reinterpret_cast<const double*>(tape),
+      reinterpret_cast<const double*>(tape + t.tape_f_offset), t.kslots,
+      (const double*)adj_out->f, adj_out->g, (double*)adj_in->f, adj_in->g, adj_tau,
+      &slot->dev->queue, s);
+  if (e == hipErrorNotSupported) return fail(POND_E_UNSUPPORTED, "pond_step_adjoint: not available");
+  if (e != hipSuccess) return hip_fail(e, "pond_step_adjoint launch");
+  return POND_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -320,6 +380,58 @@ int pond_moments(const pond_config* cfg, const pond_state* state, double* rho, d
   return POND_OK;
 }
 
+int pond_tape_bytes(const pond_config* cfg, int64_t* bytes) {
+  g_last_error.clear();
+  int rc = check_config(cfg);
+  if (rc) return rc;
+  if (!bytes) return fail(POND_E_NULL, "pond_tape_bytes: bytes is NULL");
+  *bytes = (int64_t)tape_layout(*cfg).total;
+  return POND_OK;
+}
+
+int pond_step_record(const pond_config* cfg, const pond_state* in, pond_state* out, void* tape,
+                     void* hip_stream) {
+  g_last_error.clear();
+  int rc = check_config(cfg);
+  if (rc) return rc;
+  if (!in || !out || !in->f || !in->g || !out->f || !out->g || !out->iters || !tape)
+    return fail(POND_E_NULL, "pond_step_record: a required buffer is NULL");
+  const size_t fb = f_bytes(*cfg), gb = g_bytes(*cfg), plane = (size_t)cfg->nx * cfg->ny;
+  const size_t tb = tape_layout(*cfg).total;
+  if (overlap(in->f, fb, out->f, fb) || overlap(in->g, gb, out->g, gb) ||
+      overlap(in->f, fb, out->g, gb) || overlap(in->g, gb, out->f, fb) ||
+      overlap(tape, tb, in->f, fb) || overlap(tape, tb, in->g, gb) ||
+      overlap(tape, tb, out->f, fb) || overlap(tape, tb, out->g, gb) ||
+      overlap(tape, tb, out->iters, plane))
+    return fail(POND_E_ALIAS, "pond_step_record: buffers overlap");
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  Slot* slot = nullptr;
+  if ((rc = slot_for_stream(s, &slot))) return rc;
+  if ((rc = ensure_tile_arrays(slot, pond::step_tile_count(*cfg), s))) return rc;
+  const hipError_t e = record_step(*cfg, slot, in->f, in->g, out->f, out->g, out->iters,
+                                   static_cast<char*>(tape), s);
+  if (e != hipSuccess) return hip_fail(e, "pond_step_record launch");
+  return POND_OK;
+}
+
+int pond_step_adjoint_recorded(const pond_config* cfg, const pond_state* in,
+                               const pond_state* out_fwd, const void* tape,
+                               const pond_state* adj_out, pond_state* adj_in, double* adj_tau,
+                               void* hip_stream) {
+  g_last_error.clear();
+  int rc = check_config(cfg);
+  if (rc) return rc;
+  if (!in || !out_fwd || !tape || !adj_out || !adj_in || !in->f || !in->g || !out_fwd->iters ||
+      !adj_out->f || !adj_out->g || !adj_in->f || !adj_in->g)
+    return fail(POND_E_NULL, "pond_step_adjoint_recorded: a required buffer is NULL");
+  if ((rc = check_adjoint_aliasing(*cfg, in, adj_out, adj_in, tape))) return rc;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  Slot* slot = nullptr;
+  if ((rc = slot_for_stream(s, &slot))) return rc;
+  return launch_adjoint_on(*cfg, slot, in, out_fwd->iters, static_cast<const char*>(tape),
+                           adj_out, adj_in, adj_tau, s);
+}
+
 int pond_step_adjoint(const pond_config* cfg, const pond_state* in, const pond_state* out_fwd,
                       const pond_state* adj_out, pond_state* adj_in, double* adj_tau,
                       void* hip_stream) {
@@ -329,49 +441,26 @@ int pond_step_adjoint(const pond_config* cfg, const pond_state* in, const pond_s
   if (!in || !out_fwd || !adj_out || !adj_in || !in->f || !in->g || !out_fwd->iters ||
       !adj_out->f || !adj_out->g || !adj_in->f || !adj_in->g)
     return fail(POND_E_NULL, "pond_step_adjoint: a required buffer is NULL");
-  const size_t plane = (size_t)cfg->nx * cfg->ny;
-  const size_t afb = plane * cfg->q1d * cfg->q1d * sizeof(double), agb = g_bytes(*cfg);
-  const size_t fb = f_bytes(*cfg);
-  if (overlap(adj_in->f, afb, adj_out->f, afb) || overlap(adj_in->g, agb, adj_out->g, agb) ||
-      overlap(adj_in->f, afb, in->f, fb) || overlap(adj_in->g, agb, in->g, agb) ||
-      overlap(adj_in->f, afb, adj_in->g, agb))
-    return fail(POND_E_ALIAS, "pond_step_adjoint: adj_in overlaps another buffer");
+  if ((rc = check_adjoint_aliasing(*cfg, in, adj_out, adj_in, nullptr))) return rc;
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   Slot* slot = nullptr;
   if ((rc = slot_for_stream(s, &slot))) return rc;
   if ((rc = ensure_tile_arrays(slot, pond::step_tile_count(*cfg), s))) return rc;
   // The step is run again with its pass history recorded (it reproduces
-  // out_fwd bit for bit); scratch: history, last populations, output state.
-  const int kslots = 1 + (cfg->fixed_iter > 0 ? cfg->fixed_iter : cfg->max_iter);
-  const size_t q = (size_t)cfg->q1d * cfg->q1d;
-  const size_t tape_b = (size_t)kslots * 4 * plane * sizeof(double);
-  const size_t tapef_b = q * plane * sizeof(double);
+  // out_fwd bit for bit) into the stream's scratch: tape, output state.
+  const size_t plane = (size_t)cfg->nx * cfg->ny;
+  const size_t fb = f_bytes(*cfg), gb = g_bytes(*cfg);
   const size_t align = 256;
   auto up = [&](size_t b) { return (b + align - 1) / align * align; };
-  const size_t total = up(tape_b) + up(tapef_b) + up(fb) + up(agb) + up(plane);
-  if ((rc = ensure_adjoint_scratch(slot, total, s))) return rc;
+  const size_t tb = up(tape_layout(*cfg).total);
+  if ((rc = ensure_adjoint_scratch(slot, tb + up(fb) + up(gb) + up(plane), s))) return rc;
   char* m = static_cast<char*>(slot->adj_mem);
-  double* tape = reinterpret_cast<double*>(m);
-  double* tape_f = reinterpret_cast<double*>(m + up(tape_b));
-  void* sf = m + up(tape_b) + up(tapef_b);
-  double* sg = reinterpret_cast<double*>(m + up(tape_b) + up(tapef_b) + up(fb));
-  uint8_t* siters = reinterpret_cast<uint8_t*>(m + up(tape_b) + up(tapef_b) + up(fb) + up(agb));
-  pond::StepArgs a = step_args(*cfg, slot);
-  a.f_in = in->f;
-  a.g_in = in->g;
-  a.f_out = sf;
-  a.g_out = sg;
-  a.iters = siters;
-  a.tape = tape;
-  a.tape_f = tape_f;
-  hipError_t e = launch_step_on(*cfg, slot, a, s);
+  void* sf = m + tb;
+  double* sg = reinterpret_cast<double*>(m + tb + up(fb));
+  uint8_t* siters = reinterpret_cast<uint8_t*>(m + tb + up(fb) + up(gb));
+  const hipError_t e = record_step(*cfg, slot, in->f, in->g, sf, sg, siters, m, s);
   if (e != hipSuccess) return hip_fail(e, "pond_step_adjoint step launch");
-  e = pond::launch_adjoint(*cfg, in->f, in->g, siters, tape, tape_f, (const double*)adj_out->f,
-                           adj_out->g, (double*)adj_in->f, adj_in->g, adj_tau, &slot->dev->queue,
-                           s);
-  if (e == hipErrorNotSupported) return fail(POND_E_UNSUPPORTED, "pond_step_adjoint: not available");
-  if (e != hipSuccess) return hip_fail(e, "pond_step_adjoint launch");
-  return POND_OK;
+  return launch_adjoint_on(*cfg, slot, in, siters, m, adj_out, adj_in, adj_tau, s);
 }
 
 }  // extern "C"

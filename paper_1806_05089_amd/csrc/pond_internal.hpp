@@ -72,10 +72,12 @@ hipError_t launch_moments(const pond_config& c, const void* f, const double* g, 
                           double* ux, double* uy, double* T, double* Mmn, hipStream_t s);
 hipError_t launch_zero_u64(unsigned long long* p, int n, hipStream_t s);
 // Adjoint of one step; iters, tape and tape_f are the pass counts and the
-// pass history that a step with the same input and configuration recorded.
+// pass history that a step with the same input and configuration recorded
+// (tape_slots gauge slots per node: nodes with more passes get no derivative).
 hipError_t launch_adjoint(const pond_config& c, const void* f_in, const double* g_in,
                           const uint8_t* iters, const double* tape, const double* tape_f,
-                          const double* adj_f_out, const double* adj_g_out, double* adj_f_in,
-                          double* adj_g_in, double* adj_tau, TileQueue* queue, hipStream_t s);
+                          int tape_slots, const double* adj_f_out, const double* adj_g_out,
+                          double* adj_f_in, double* adj_g_in, double* adj_tau, TileQueue* queue,
+                          hipStream_t s);
 
 }  // namespace pond

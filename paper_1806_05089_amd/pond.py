@@ -161,5 +161,60 @@ def step_adjoint(cfg: PondConfig, state_in: PondState, state_out: PondState,
     return a_in_f, a_in_g
 
 
+def tape_bytes(cfg: PondConfig) -> int:
+    """pond_tape_bytes: size of one recorded step's pass history."""
+    n = C.c_int64(0)
+    _lib.check(_lib.load().pond_tape_bytes(C.byref(cfg.c()), C.byref(n)))
+    return int(n.value)
+
+
+def step_record(cfg: PondConfig, state_in: PondState, state_out: PondState | None = None,
+                tape: torch.Tensor | None = None):
+    """pond_step_record: one step that also records its pass history.
+
+    Returns (state_out, tape); tape is a uint8 device tensor of tape_bytes(cfg)
+    bytes (allocated when not given)."""
+    lib = _lib.load()
+    _check_state(cfg, state_in, "state_in")
+    dev = state_in.f.device
+    if state_out is None:
+        state_out = empty_state(cfg, dev)
+    _check_state(cfg, state_out, "state_out")
+    if state_out.iters is None:
+        raise ValueError("step_record: state_out.iters is required")
+    nb = tape_bytes(cfg)
+    if tape is None:
+        tape = torch.empty(nb, dtype=torch.uint8, device=dev)
+    _require(tape, (nb,), torch.uint8, "tape")
+    cin, cout = state_in.c(), state_out.c()
+    _lib.check(lib.pond_step_record(C.byref(cfg.c()), C.byref(cin), C.byref(cout),
+                                    tape.data_ptr(), _stream_ptr(dev)))
+    return state_out, tape
+
+
+def step_adjoint_recorded(cfg: PondConfig, state_in: PondState, state_out: PondState,
+                          tape: torch.Tensor, adj_f: torch.Tensor, adj_g: torch.Tensor,
+                          adj_tau: torch.Tensor | None = None):
+    """pond_step_adjoint_recorded: step_adjoint about a step_record step."""
+    lib = _lib.load()
+    _check_state(cfg, state_in, "state_in")
+    _check_state(cfg, state_out, "state_out")
+    _require(tape, (tape_bytes(cfg),), torch.uint8, "tape")
+    _require(adj_f, (cfg.Q, cfg.ny, cfg.nx), torch.float64, "adj_f")
+    _require(adj_g, (3, cfg.ny, cfg.nx), torch.float64, "adj_g")
+    if adj_tau is not None:
+        _require(adj_tau, (1,), torch.float64, "adj_tau")
+    a_in_f = torch.empty_like(adj_f)
+    a_in_g = torch.empty_like(adj_g)
+    s_in, s_out = state_in.c(), state_out.c()
+    a_out = _lib.pond_state(adj_f.data_ptr(), adj_g.data_ptr(), None)
+    a_in = _lib.pond_state(a_in_f.data_ptr(), a_in_g.data_ptr(), None)
+    _lib.check(lib.pond_step_adjoint_recorded(
+        C.byref(cfg.c()), C.byref(s_in), C.byref(s_out), tape.data_ptr(), C.byref(a_out),
+        C.byref(a_in), adj_tau.data_ptr() if adj_tau is not None else None,
+        _stream_ptr(state_in.f.device)))
+    return a_in_f, a_in_g
+
+
 def abi_version() -> int:
     return _lib.load().pond_abi_version()

@@ -131,6 +131,29 @@ def test_null_and_alias_checks(lib):
     a_out = _state(f2, g2)
     assert lib.pond_step_adjoint(C.byref(cfg), C.byref(s_in), C.byref(s_in), C.byref(a_out),
                                  C.byref(a_out), None, None) == _lib.POND_E_NULL
+    # recorded steps: the tape, and the output's pass counts, are required
+    assert lib.pond_tape_bytes(C.byref(cfg), None) == _lib.POND_E_NULL
+    tape = (C.c_uint8 * 4096)()
+    assert lib.pond_step_record(C.byref(cfg), C.byref(s_in), C.byref(s_out), None,
+                                None) == _lib.POND_E_NULL
+    assert lib.pond_step_record(C.byref(cfg), C.byref(s_in), C.byref(s_out), tape,
+                                None) == _lib.POND_E_NULL  # s_out.iters is NULL
+    assert lib.pond_step_adjoint_recorded(C.byref(cfg), C.byref(s_in), C.byref(s_in), None,
+                                          C.byref(a_out), C.byref(a_out), None,
+                                          None) == _lib.POND_E_NULL
+
+
+def test_tape_bytes(lib):
+    """((K + 1) * 4 + q^2) * nx * ny doubles, K = fixed_iter or max_iter."""
+    n = C.c_int64(0)
+    cfg = _cfg(nx=10, ny=6, max_iter=20)
+    assert lib.pond_tape_bytes(C.byref(cfg), C.byref(n)) == _lib.POND_OK
+    assert n.value == (21 * 4 + 16) * 60 * 8
+    cfg = _cfg(nx=10, ny=6, q1d=3, fixed_iter=3)
+    assert lib.pond_tape_bytes(C.byref(cfg), C.byref(n)) == _lib.POND_OK
+    assert n.value == (4 * 4 + 9) * 60 * 8
+    cfg = _cfg(nx=10, ny=6, max_iter=0)
+    assert lib.pond_tape_bytes(C.byref(cfg), C.byref(n)) == _lib.POND_E_INVALID
 
 
 def test_python_binding_fails_loudly_without_library(tmp_path):

@@ -192,3 +192,31 @@ def test_rollout_gradient_vs_complex_step(gpu):
 
     fd = (J_gpu(w.ux + h * d, 0.6) - J_gpu(w.ux - h * d, 0.6)) / (2 * h)
     assert abs(fd - rhs) <= 1e-6 * abs(rhs), (fd, rhs)
+
+
+@pytest.mark.parametrize("prec", [pond.POND_F64, pond.POND_F32_MIXED])
+def test_recorded_step_and_adjoint(gpu, prec):
+    """pond_step_record is pond_step bit for bit, and the adjoint about the
+    recorded step equals pond_step_adjoint (which records the step itself) to
+    rounding (both add with floating-point atomics)."""
+    w = workloads.riemann2d(48, seed=3)
+    cfg = pond.PondConfig(nx=48, ny=48, bc_x=1, bc_y=1, tau=0.55, max_iter=20, precision=prec)
+    if prec == pond.POND_F32_MIXED:
+        cfg = cfg.replace(eps_abs=1e-6, eps_rel=1e-5)
+    st = pond.init(cfg, w.rho, w.ux, w.uy, w.T)
+    st, _ = pond.step(cfg, st, nsteps=4)
+    ref, _ = pond.step(cfg, st.clone())
+    rec, tape = pond.step_record(cfg, st.clone())
+    assert tape.numel() == pond.tape_bytes(cfg)
+    assert torch.equal(rec.f, ref.f) and torch.equal(rec.g, ref.g)
+    assert torch.equal(rec.iters, ref.iters)
+    gen = torch.Generator(device="cuda").manual_seed(9)
+    wf = torch.randn(ref.f.shape, dtype=torch.float64, device="cuda", generator=gen)
+    wg = torch.randn(ref.g.shape, dtype=torch.float64, device="cuda", generator=gen)
+    t1 = torch.zeros(1, dtype=torch.float64, device="cuda")
+    t2 = torch.zeros(1, dtype=torch.float64, device="cuda")
+    f1, g1 = pond.step_adjoint(cfg, st, ref, wf, wg, t1)
+    f2, g2 = pond.step_adjoint_recorded(cfg, st, rec, tape, wf, wg, t2)
+    for a, b in ((f2, f1), (g2, g1)):
+        assert float(torch.max(torch.abs(a - b))) <= 1e-12 * float(torch.max(torch.abs(b)))
+    assert abs(float(t2) - float(t1)) <= 1e-12 * abs(float(t1))
