@@ -182,7 +182,8 @@ int pond_step_adjoint_recorded(const pond_config* cfg, const pond_state* in,
 /* Message for the last nonzero return on this thread ("" if none). */
 const char* pond_last_error(void);
 
-/* ABI version of this header (major * 100 + minor). */
+/* ABI version of this header (major * 100 + minor): 101 adds the recorded
+ * steps (pond_tape_bytes, pond_step_record, pond_step_adjoint_recorded). */
 int pond_abi_version(void);
 
 #ifdef __cplusplus

@@ -276,7 +276,7 @@ extern "C" {
 
 const char* pond_last_error(void) { return g_last_error.c_str(); }
 
-int pond_abi_version(void) { return 100; }
+int pond_abi_version(void) { return 101; }
 
 int pond_init(const pond_config* cfg, const double* rho, const double* ux, const double* uy,
               const double* T, pond_state* out, void* hip_stream) {

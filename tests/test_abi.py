@@ -71,7 +71,7 @@ int main(void) {
 
 
 def test_abi_version(lib):
-    assert lib.pond_abi_version() == 100
+    assert lib.pond_abi_version() == 101
 
 
 def _cfg(**kw):
