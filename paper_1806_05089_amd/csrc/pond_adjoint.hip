@@ -141,7 +141,10 @@ __device__ __forceinline__ void interp_weight_n(int n, double t, double& a, doub
   const double e1 = t - (n == 0 ? 1.0 : 0.0);
   const double e2 = t - (n <= 1 ? 2.0 : 1.0);
   const double e3 = t - (n <= 2 ? 3.0 : 2.0);
-  const double cn = n == 0 ? -1.0 / 6.0 : n == 1 ? 0.5 : n == 2 ? -0.5 : 1.0 / 6.0;
+  // the constant factor as a sign and a magnitude (two-way selects; a
+  // four-way chain on n is compiled into branches)
+  const double mag = ((n + 1) & 2) == 0 ? 1.0 / 6.0 : 0.5;  // nodes 0, 3 : 1, 2
+  const double cn = (n & 1) ? mag : -mag;
   a = e1 * e2 * e3 * cn;
   da = (e2 * e3 + e1 * e3 + e1 * e2) * cn;
 }
