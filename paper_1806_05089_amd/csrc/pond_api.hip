@@ -122,7 +122,7 @@ int bulk_cap(int precision) {
     return e ? atoi(e) : -1;
   }();
   if (env >= 0) return env;
-  return precision == POND_F64 ? 5 : 3;
+  return precision == POND_F64 ? 7 : 3;
 }
 
 size_t f_bytes(const pond_config& c) {
