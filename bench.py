@@ -43,7 +43,9 @@ FLOPS_PER_NODE_STEP = 560
 PEAK_FP64_TFLOPS = 78.6   # MI355X vector FP64: 256 CU x 2.4 GHz x 64 lanes x 2
 PEAK_FP32_TFLOPS = 157.3  # MI355X published FP32 peak
 PEAK_HBM_GBPS = 8000.0    # MI355X HBM3E
-STEP_SOURCE = os.path.join(ROOT, "paper_1806_05089_amd", "csrc", "pond_step.hip")
+# the step kernel, its device helpers and the launch settings (bulk cap)
+STEP_SOURCES = [os.path.join(ROOT, "paper_1806_05089_amd", "csrc", n)
+                for n in ("pond_step.hip", "pond_device.hpp", "pond_api.hip")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_riemann2d_1024_fp64_hbm_traffic.json")
 
 
@@ -52,7 +54,10 @@ def log(msg):
 
 
 def source_digest():
-    return hashlib.sha256(open(STEP_SOURCE, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for path in STEP_SOURCES:
+        h.update(open(path, "rb").read())
+    return h.hexdigest()[:16]
 
 
 def make_cfg(w, precision, q1d=4):
