@@ -253,6 +253,32 @@ def test_full_size_sampled_riemann_1024(gpu):
         assert max(errs.values()) < tol, (prec, errs)
 
 
+def test_full_size_sampled_riemann_1024_adaptive(gpu):
+    """The benchmark's own configuration (adaptive passes, 16-lane tail) on the
+    1024^2 Riemann input: sampled nodes, including the 64 that take the most
+    passes (they finish in the tail), against the oracle.  Pass counts agree at
+    almost every node; where they do the states agree to 1e-9."""
+    w = workloads.riemann2d(1024, seed=3)
+    cfg = _cfg(w, max_iter=20)
+    st = pond.init(cfg, w.rho, w.ux, w.uy, w.T)
+    st, _ = pond.step(cfg, st, nsteps=20)
+    out, _ = pond.step(cfg, st.clone())
+    f_in = st.f.double().cpu().numpy()
+    g_in = st.g.cpu().numpy()
+    it = out.iters.cpu().numpy().reshape(-1) & pond.POND_ITERS_MASK
+    rng = np.random.default_rng(1)
+    pts = np.concatenate([np.argsort(it)[-64:], rng.integers(0, it.size, 192)]).astype(np.int64)
+    assert it[pts[:64]].max() > 7  # past the bulk-pass cap: finished in the tail
+    fo, go, io, _ = oracle.step_nodes(f_in, g_in, _ocfg(cfg), pts)
+    same = (io & pond.POND_ITERS_MASK) == it[pts]
+    assert np.mean(same) >= 0.95, np.mean(same)
+    fg = out.f.double().cpu().numpy().reshape(16, -1)[:, pts]
+    gg = out.g.cpu().numpy().reshape(3, -1)[:, pts]
+    errs = state_errors(fg[:, same], gg[:, same], fo[:, same], go[:, same], u_scale=1.0,
+                        T_scale=float(np.max(w.T)))
+    assert max(errs.values()) < 1e-9, errs
+
+
 def _far_base(q):
     return workloads.random_smooth(48, 40, seed=13, mach=0.3, T0=1.0 if q == 4 else 1.0 / 3.0)
 
