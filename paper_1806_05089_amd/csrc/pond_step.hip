@@ -637,19 +637,32 @@ k_step(StepArgs A) {
     // ---- stage the window in the reference gauge (eq. 4, G_{s->B}) ----
     {
       const double inv_sB = 1.0 / sB;
-      for (int k = tid; k < WN; k += NT) {
+      // the reads of a thread's next window node are issued before the
+      // current one is transformed, so that their latency overlaps it
+      FT fn[Q];
+      double gn[3];
+      auto fetch = [&](int k) {
         const int wy = k / WX, wx = k - wy * WX;
         const int sx = wrap_index(wx0 + wx, A.nx, A.bc_x);
         const int sy = wrap_index(wy0 + wy, A.ny, A.bc_y);
         const size_t src = (size_t)sy * A.nx + sx;
+#pragma unroll
+        for (int p = 0; p < Q; ++p) fn[p] = fin[(size_t)p * plane + src];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) gn[c] = gin[c * plane + src];
+      };
+      if (tid < WN) fetch(tid);
+      for (int k = tid; k < WN; k += NT) {
         double f[Q];
 #pragma unroll
-        for (int p = 0; p < Q; ++p) f[p] = double(fin[(size_t)p * plane + src]);
-        const double ss = sqrt(gin[2 * plane + src] * L::inv_TL);
+        for (int p = 0; p < Q; ++p) f[p] = double(fn[p]);
+        const double gux = gn[0], guy = gn[1], gT = gn[2];
+        if (k + NT < WN) fetch(k + NT);
+        const double ss = sqrt(gT * L::inv_TL);
         const double r = ss * inv_sB;
         double Gx[Q], Gy[Q];
-        transfer_factor<Q1, double>(r, (gin[src] - uxB) * inv_sB, Gx);
-        transfer_factor<Q1, double>(r, (gin[plane + src] - uyB) * inv_sB, Gy);
+        transfer_factor<Q1, double>(r, (gux - uxB) * inv_sB, Gx);
+        transfer_factor<Q1, double>(r, (guy - uyB) * inv_sB, Gy);
         double Hm[Q];  // Hm[i][l] = sum_j Gy[l][j] f[i][j]
 #pragma unroll
         for (int i = 0; i < Q1; ++i)
