@@ -170,25 +170,22 @@ __device__ __forceinline__ double speed_rt(int i) {
 // ----------------------------------------------- reconstruction (App. C)
 // Third-order Lagrange weights on the four collocation points x0 + n,
 // x0 = floor(x) - 1, at local coordinate t = x - x0 in [1, 2).
-// Weight of stencil node n (0..3) for a per-lane n: the same products as
-// interp_weight_at, the constant factor a sign and a magnitude picked by
-// two-way selects (a four-way chain on n is compiled into branches).
-__device__ __forceinline__ double interp_weight_sel(int n, double t) {
-  const double e1 = t - (n == 0 ? 1.0 : 0.0);
-  const double e2 = t - (n <= 1 ? 2.0 : 1.0);
-  const double e3 = t - (n <= 2 ? 3.0 : 2.0);
-  const double mag = ((n + 1) & 2) == 0 ? 1.0 / 6.0 : 0.5;  // nodes 0, 3 : 1, 2
-  return e1 * e2 * e3 * ((n & 1) ? mag : -mag);
+// Cubic Lagrange weight of a stencil node at signed distance u from the
+// departure point (node minus point), as one function of |u| (App. C): the
+// four-node stencil around the point is symmetric, so the weight is
+// (|u|+1)(|u|-1)(|u|-2)/2 for |u| <= 1, -(|u|-1)(|u|-2)(|u|-3)/6 for
+// 1 < |u| < 2, and the node is outside the stencil (in = false, weight 0)
+// beyond.  Evaluated in FT from |u| (FP32: |u| rounded once).
+template <class FT>
+__device__ __forceinline__ FT lagrange_weight(double u, bool& in) {
+  const FT a = FT(fabs(u));
+  const FT near = fma(fma(fma(FT(0.5), a, FT(-1.0)), a, FT(-0.5)), a, FT(1.0));
+  const FT far = fma(fma(fma(FT(-1.0 / 6.0), a, FT(1.0)), a, FT(-11.0 / 6.0)), a, FT(1.0));
+  in = a < FT(2.0);
+  const FT w = a <= FT(1.0) ? near : far;
+  return in ? w : FT(0);
 }
-// The same, zero for n outside 0..3, without a branch.
-__device__ __forceinline__ double interp_weight_masked(int n, double t) {
-  const double e1 = t - (n == 0 ? 1.0 : 0.0);
-  const double e2 = t - (n <= 1 ? 2.0 : 1.0);
-  const double e3 = t - (n <= 2 ? 3.0 : 2.0);
-  const double mag = ((n + 1) & 2) == 0 ? 1.0 / 6.0 : 0.5;
-  const double cn = (n & 1) ? mag : -mag;
-  return e1 * e2 * e3 * ((unsigned)n < 4u ? cn : 0.0);
-}
+
 __device__ __forceinline__ void interp_weights(double t, double* a) {
   const double t0 = t, t1 = t - 1.0, t2 = t - 2.0, t3 = t - 3.0;
   a[0] = t1 * t2 * t3 * (-1.0 / 6.0);

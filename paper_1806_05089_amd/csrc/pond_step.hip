@@ -725,7 +725,7 @@ k_step(StepArgs A) {
         // a2 + a3 (x axis) for every x speed: departure columns x0_i (as offsets
         // o_i = x0_i - X), weights, and the rows of G_{B->n} along x.
         int o[Q1];
-        double tx[Q1];  // departure coordinate in its stencil (weights per column)
+        double xdv[Q1];  // departure abscissae (weights per column)
         FT gbx[Q1][Q1];
         int lo = INT_MAX, hi = INT_MIN;
         bool has = false, far = false;
@@ -733,7 +733,7 @@ k_step(StepArgs A) {
         for (int i = 0; i < Q1; ++i) {
           const double xd = double(X) - (s * L::c(i) + ux);
           const double fl = floor(xd);
-          tx[i] = xd - (fl - 1.0);
+          xdv[i] = xd;
           o[i] = sat_floor(fl) - 1 - X;
           double row[Q1];
           transfer_row<Q1>(i, rB, dBx, row);
@@ -795,16 +795,11 @@ k_step(StepArgs A) {
           for (int rel = lo; rel <= hi; ++rel) {
             FT wx[Q1];
             bool need = false;
+            const double px = double(X + rel);
 #pragma unroll
             for (int i = 0; i < Q1; ++i) {
-              const int n = rel - o[i];
-              const bool in = (unsigned)n < 4u;
-              // FP64: a wave skips the weight of a speed none of its lanes
-              // needs (measured faster); FP32: branch-free
-              if constexpr (sizeof(FT) == 8)
-                wx[i] = in ? FT(interp_weight_sel(n, tx[i])) : FT(0);
-              else
-                wx[i] = FT(interp_weight_masked(n, tx[i]));
+              bool in;
+              wx[i] = lagrange_weight<FT>(px - xdv[i], in);
               need = need || in;
             }
             if (!__any(need)) continue;
