@@ -760,37 +760,40 @@ k_step(StepArgs A) {
         // speeds (each with its own weight, zero where the column is outside
         // that speed's stencil).
         if (!wave_column_range(lo, hi, has, lo, hi)) hi = lo - 1;
-        // y speeds per column walk (the column's weights, tests and addresses
-        // serve them all, and their rows are read interleaved): D2Q16 two
-        // (measured faster than one or four), D2Q9 all three
+        // y speeds are taken in groups of JB (a group's rows are read
+        // interleaved): D2Q16 two groups of two (measured faster than one or
+        // four per group), D2Q9 one group of three.
         constexpr int JB = Q1 % 2 == 0 ? 2 : 3;
-#pragma unroll 1
-        for (int j0 = 0; j0 < Q1; j0 += JB) {
-          FT ayw[JB][4];
-          int y0[JB], ly0[JB];
-          bool rows_in[JB];
-          LagRow Pj[JB];
-          FT gby[JB][Q1];
-          FT acc_row[JB][Q1];
-          bool all_in = true;
+        if constexpr (sizeof(FT) == 4) {
+          // FP32-mixed: one column walk for every group (a column's x weights
+          // serve them all; measured faster than a walk per group)
+          constexpr int NG = Q1 / JB;
+          FT ayw[Q1][4];
+          int y0[Q1], ly0[Q1];
+          bool rows_in[Q1];
+          FT gby[Q1][Q1];
+          bool all_in[NG];
 #pragma unroll
-          for (int b = 0; b < JB; ++b) {
+          for (int g = 0; g < NG; ++g) all_in[g] = true;
+#pragma unroll
+          for (int j = 0; j < Q1; ++j) {
             // a2 + a3 (y axis): the departure ordinate depends on c_j only.
-            const int j = j0 + b;
-            const double yd = double(Y) - (s * speed_rt<Q1>(j) + uy);
+            const double yd = double(Y) - (s * L::c(j) + uy);
             const double fly = floor(yd);
             const double ty = yd - (fly - 1.0);
 #pragma unroll
-            for (int m = 0; m < 4; ++m) ayw[b][m] = FT(interp_weight_at(m, ty));
-            y0[b] = sat_floor(fly) - 1;
-            ly0[b] = y0[b] - wy0;
-            rows_in[b] = (unsigned)ly0[b] <= (unsigned)(WY - 4);
-            all_in = all_in && rows_in[b];
-            Pj[b] = lag_row<Q1>(j);
-            row_to<Q1, FT>(Pj[b], rB, dBy, gby[b]);
-#pragma unroll
-            for (int i = 0; i < Q1; ++i) acc_row[b][i] = FT(0);
+            for (int m = 0; m < 4; ++m) ayw[j][m] = FT(interp_weight_at(m, ty));
+            y0[j] = sat_floor(fly) - 1;
+            ly0[j] = y0[j] - wy0;
+            rows_in[j] = (unsigned)ly0[j] <= (unsigned)(WY - 4);
+            all_in[j / JB] = all_in[j / JB] && rows_in[j];
+            row_to<Q1, FT>(lag_row<Q1>(j), rB, dBy, gby[j]);
           }
+          FT acc[Q1][Q1];  // acc[j][i]: population (i, j) of the pass
+#pragma unroll
+          for (int j = 0; j < Q1; ++j)
+#pragma unroll
+            for (int i = 0; i < Q1; ++i) acc[j][i] = FT(0);
 #pragma unroll 1
           for (int rel = lo; rel <= hi; ++rel) {
             FT wx[Q1];
@@ -803,56 +806,152 @@ k_step(StepArgs A) {
               need = need || in;
             }
             if (!__any(need)) continue;
-            FT hc[JB][Q1];
-#pragma unroll
-            for (int b = 0; b < JB; ++b)
-#pragma unroll
-              for (int ip = 0; ip < Q1; ++ip) hc[b][ip] = FT(0);
             const int lx = X + rel - wx0;
             const bool col_in = (unsigned)lx < (unsigned)WX;
-            if (need && all_in && col_in) {
-              int kk[JB];
 #pragma unroll
-              for (int b = 0; b < JB; ++b) kk[b] = ly0[b] * WX + lx;
-              window_columns<Q1, JB, FT, WX, WN>(s_f, kk, ayw, gby, hc);
-            } else if (need) {
+            for (int g = 0; g < NG; ++g) {
+              const int j0 = g * JB;
+              FT hc[JB][Q1];
 #pragma unroll
-              for (int b = 0; b < JB; ++b) {
-                // with one speed per walk this path means the column leaves the window
-                if (JB > 1 && rows_in[b] && col_in) {
-                  const int kk = ly0[b] * WX + lx;
-                  window_columns<Q1, 1, FT, WX, WN>(s_f, &kk, &ayw[b], &gby[b], &hc[b]);
-                } else {
+              for (int b = 0; b < JB; ++b)
+#pragma unroll
+                for (int ip = 0; ip < Q1; ++ip) hc[b][ip] = FT(0);
+              if (need && all_in[g] && col_in) {
+                int kk[JB];
+#pragma unroll
+                for (int b = 0; b < JB; ++b) kk[b] = ly0[j0 + b] * WX + lx;
+                window_columns<Q1, JB, FT, WX, WN>(s_f, kk, &ayw[j0], &gby[j0], hc);
+              } else if (need) {
+#pragma unroll
+                for (int b = 0; b < JB; ++b) {
+                  const int j = j0 + b;
+                  // with one speed per group this path means the column leaves the window
+                  if (JB > 1 && rows_in[j] && col_in) {
+                    const int kq = ly0[j] * WX + lx;
+                    window_columns<Q1, 1, FT, WX, WN>(s_f, &kq, &ayw[j], &gby[j], &hc[b]);
+                  } else {
+                    const LagRow Pj = lag_row<Q1>(j);
 #pragma unroll 1
-                  for (int m = 0; m < 4; ++m) {
-                    const FT aym = m == 0   ? ayw[b][0]
-                                   : m == 1 ? ayw[b][1]
-                                   : m == 2 ? ayw[b][2]
-                                            : ayw[b][3];
-                    column_point<Q1, FT, WX, WY, WN>(A, s_f, wx0, wy0, X + rel, y0[b] + m, true,
-                                                     aym, wx, gby[b], Pj[b], ux, uy, inv_s, hc[b],
-                                                     acc_row[b]);
+                    for (int m = 0; m < 4; ++m) {
+                      const FT aym = m == 0   ? ayw[j][0]
+                                     : m == 1 ? ayw[j][1]
+                                     : m == 2 ? ayw[j][2]
+                                              : ayw[j][3];
+                      column_point<Q1, FT, WX, WY, WN>(A, s_f, wx0, wy0, X + rel, y0[j] + m,
+                                                       true, aym, wx, gby[j], Pj, ux, uy, inv_s,
+                                                       hc[b], acc[j]);
+                    }
                   }
                 }
               }
+#pragma unroll
+              for (int b = 0; b < JB; ++b)
+#pragma unroll
+                for (int i = 0; i < Q1; ++i) {
+                  FT v = FT(0);
+#pragma unroll
+                  for (int ip = 0; ip < Q1; ++ip) v += gbx[i][ip] * hc[b][ip];
+                  acc[j0 + b][i] += wx[i] * v;
+                }
+            }
+          }
+#pragma unroll
+          for (int i = 0; i < Q1; ++i)
+#pragma unroll
+            for (int j = 0; j < Q1; ++j) ft[i * Q1 + j] = acc[j][i];
+        } else {
+          // FP64: one column walk per group, half the y state in registers
+          // (the one-walk form spills here and measured slower)
+#pragma unroll 1
+          for (int j0 = 0; j0 < Q1; j0 += JB) {
+            FT ayw[JB][4];
+            int y0[JB], ly0[JB];
+            bool rows_in[JB];
+            LagRow Pj[JB];
+            FT gby[JB][Q1];
+            FT acc_row[JB][Q1];
+            bool all_in = true;
+#pragma unroll
+            for (int b = 0; b < JB; ++b) {
+              // a2 + a3 (y axis): the departure ordinate depends on c_j only.
+              const int j = j0 + b;
+              const double yd = double(Y) - (s * speed_rt<Q1>(j) + uy);
+              const double fly = floor(yd);
+              const double ty = yd - (fly - 1.0);
+#pragma unroll
+              for (int m = 0; m < 4; ++m) ayw[b][m] = FT(interp_weight_at(m, ty));
+              y0[b] = sat_floor(fly) - 1;
+              ly0[b] = y0[b] - wy0;
+              rows_in[b] = (unsigned)ly0[b] <= (unsigned)(WY - 4);
+              all_in = all_in && rows_in[b];
+              Pj[b] = lag_row<Q1>(j);
+              row_to<Q1, FT>(Pj[b], rB, dBy, gby[b]);
+#pragma unroll
+              for (int i = 0; i < Q1; ++i) acc_row[b][i] = FT(0);
+            }
+#pragma unroll 1
+            for (int rel = lo; rel <= hi; ++rel) {
+              FT wx[Q1];
+              bool need = false;
+              const double px = double(X + rel);
+#pragma unroll
+              for (int i = 0; i < Q1; ++i) {
+                bool in;
+                wx[i] = lagrange_weight<FT>(px - xdv[i], in);
+                need = need || in;
+              }
+              if (!__any(need)) continue;
+              FT hc[JB][Q1];
+#pragma unroll
+              for (int b = 0; b < JB; ++b)
+#pragma unroll
+                for (int ip = 0; ip < Q1; ++ip) hc[b][ip] = FT(0);
+              const int lx = X + rel - wx0;
+              const bool col_in = (unsigned)lx < (unsigned)WX;
+              if (need && all_in && col_in) {
+                int kk[JB];
+#pragma unroll
+                for (int b = 0; b < JB; ++b) kk[b] = ly0[b] * WX + lx;
+                window_columns<Q1, JB, FT, WX, WN>(s_f, kk, ayw, gby, hc);
+              } else if (need) {
+#pragma unroll
+                for (int b = 0; b < JB; ++b) {
+                  // with one speed per walk this path means the column leaves the window
+                  if (JB > 1 && rows_in[b] && col_in) {
+                    const int kk = ly0[b] * WX + lx;
+                    window_columns<Q1, 1, FT, WX, WN>(s_f, &kk, &ayw[b], &gby[b], &hc[b]);
+                  } else {
+#pragma unroll 1
+                    for (int m = 0; m < 4; ++m) {
+                      const FT aym = m == 0   ? ayw[b][0]
+                                     : m == 1 ? ayw[b][1]
+                                     : m == 2 ? ayw[b][2]
+                                              : ayw[b][3];
+                      column_point<Q1, FT, WX, WY, WN>(A, s_f, wx0, wy0, X + rel, y0[b] + m, true,
+                                                       aym, wx, gby[b], Pj[b], ux, uy, inv_s, hc[b],
+                                                       acc_row[b]);
+                    }
+                  }
+                }
+              }
+#pragma unroll
+              for (int b = 0; b < JB; ++b)
+#pragma unroll
+                for (int i = 0; i < Q1; ++i) {
+                  FT v = FT(0);
+#pragma unroll
+                  for (int ip = 0; ip < Q1; ++ip) v += gbx[i][ip] * hc[b][ip];
+                  acc_row[b][i] += wx[i] * v;
+                }
             }
 #pragma unroll
             for (int b = 0; b < JB; ++b)
 #pragma unroll
-              for (int i = 0; i < Q1; ++i) {
-                FT v = FT(0);
+              for (int i = 0; i < Q1; ++i)
 #pragma unroll
-                for (int ip = 0; ip < Q1; ++ip) v += gbx[i][ip] * hc[b][ip];
-                acc_row[b][i] += wx[i] * v;
-              }
+                for (int jj = 0; jj < Q1; ++jj)
+                  if (jj == j0 + b) ft[i * Q1 + jj] = acc_row[b][i];
           }
-#pragma unroll
-          for (int b = 0; b < JB; ++b)
-#pragma unroll
-            for (int i = 0; i < Q1; ++i)
-#pragma unroll
-              for (int jj = 0; jj < Q1; ++jj)
-                if (jj == j0 + b) ft[i * Q1 + jj] = acc_row[b][i];
         }
 
         // a6: moments in the peculiar frame of lambda_n (compensated sums).
