@@ -891,13 +891,23 @@ k_step(StepArgs A) {
             }
 #pragma unroll 1
             for (int rel = lo; rel <= hi; ++rel) {
+              // x speeds whose stencil no lane of the wave reaches at this
+              // column skip their weight and x contraction (wave-uniform
+              // branches; about half of them at any column)
               FT wx[Q1];
+              bool wneed[Q1];
               bool need = false;
               const double px = double(X + rel);
 #pragma unroll
               for (int i = 0; i < Q1; ++i) {
-                bool in;
-                wx[i] = lagrange_weight<FT>(px - xdv[i], in);
+                const double u = px - xdv[i];
+                const bool in = fabs(u) < 2.0;
+                wneed[i] = __any(in);
+                wx[i] = FT(0);
+                if (wneed[i]) {
+                  bool in2;
+                  wx[i] = lagrange_weight<FT>(u, in2);
+                }
                 need = need || in;
               }
               if (!__any(need)) continue;
@@ -935,14 +945,16 @@ k_step(StepArgs A) {
                 }
               }
 #pragma unroll
-              for (int b = 0; b < JB; ++b)
+              for (int i = 0; i < Q1; ++i) {
+                if (!wneed[i]) continue;
 #pragma unroll
-                for (int i = 0; i < Q1; ++i) {
+                for (int b = 0; b < JB; ++b) {
                   FT v = FT(0);
 #pragma unroll
                   for (int ip = 0; ip < Q1; ++ip) v += gbx[i][ip] * hc[b][ip];
                   acc_row[b][i] += wx[i] * v;
                 }
+              }
             }
 #pragma unroll
             for (int b = 0; b < JB; ++b)
