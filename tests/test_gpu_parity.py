@@ -279,6 +279,48 @@ def test_full_size_sampled_riemann_1024_adaptive(gpu):
     assert max(errs.values()) < 1e-9, errs
 
 
+def test_full_size_sampled_riemann_1024_d2q9(gpu):
+    """The benchmark's D2Q9 line (the Riemann input with temperatures scaled to
+    T_L = 1/3, 1024^2): both precisions with fixed passes at 384 sampled nodes,
+    then FP64 with adaptive passes after 20 steps at 256 nodes including the
+    64 that take the most passes."""
+    w = workloads.riemann2d(1024, seed=3, T_scale=workloads.TL_D2Q9)
+    N = 1024
+    rng = np.random.default_rng(5)
+    pts = list(rng.integers(0, N * N, 256))
+    for y in (0, 1, 511, 512, 1022, 1023):
+        for x in (0, 2, 510, 511, 512, 513, 1023):
+            pts.append(y * N + x)
+    pts = np.array(pts[:384], dtype=np.int64)
+    for prec, tol in ((pond.POND_F64, TOL64), (pond.POND_F32_MIXED, 2e-6)):
+        cfg = _cfg(w, q=3, precision=prec, max_iter=20, fixed_iter=3)
+        if prec == pond.POND_F32_MIXED:
+            cfg = cfg.replace(eps_abs=1e-6, eps_rel=1e-5)
+        st = pond.init(cfg, w.rho, w.ux, w.uy, w.T)
+        out, _ = pond.step(cfg, st)
+        fo, go, _, _ = oracle.step_nodes(st.f.double().cpu().numpy(), st.g.cpu().numpy(),
+                                         _ocfg(cfg), pts)
+        fg = out.f.double().cpu().numpy().reshape(9, -1)[:, pts]
+        gg = out.g.cpu().numpy().reshape(3, -1)[:, pts]
+        errs = state_errors(fg, gg, fo, go, u_scale=1.0, T_scale=float(np.max(w.T)))
+        assert max(errs.values()) < tol, (prec, errs)
+    cfg = _cfg(w, q=3, max_iter=20)
+    st = pond.init(cfg, w.rho, w.ux, w.uy, w.T)
+    st, _ = pond.step(cfg, st, nsteps=20)
+    out, _ = pond.step(cfg, st.clone())
+    it = out.iters.cpu().numpy().reshape(-1) & pond.POND_ITERS_MASK
+    sel = np.concatenate([np.argsort(it)[-64:], rng.integers(0, it.size, 192)]).astype(np.int64)
+    fo, go, io, _ = oracle.step_nodes(st.f.double().cpu().numpy(), st.g.cpu().numpy(),
+                                      _ocfg(cfg), sel)
+    same = (io & pond.POND_ITERS_MASK) == it[sel]
+    assert np.mean(same) >= 0.95, np.mean(same)
+    fg = out.f.double().cpu().numpy().reshape(9, -1)[:, sel]
+    gg = out.g.cpu().numpy().reshape(3, -1)[:, sel]
+    errs = state_errors(fg[:, same], gg[:, same], fo[:, same], go[:, same], u_scale=1.0,
+                        T_scale=float(np.max(w.T)))
+    assert max(errs.values()) < 1e-9, errs
+
+
 def _far_base(q):
     return workloads.random_smooth(48, 40, seed=13, mach=0.3, T0=1.0 if q == 4 else 1.0 / 3.0)
 
