@@ -253,6 +253,32 @@ def test_full_size_sampled_riemann_1024(gpu):
         assert max(errs.values()) < tol, (prec, errs)
 
 
+def test_full_size_sampled_riemann_2048(gpu):
+    """The 2048^2 Riemann input (the largest benchmark grid, 8192 tiles): both
+    precisions with fixed passes at 320 sampled nodes, tile seams and corners."""
+    N = 2048
+    w = workloads.riemann2d(N, seed=3)
+    rng = np.random.default_rng(7)
+    pts = list(rng.integers(0, N * N, 256))
+    for y in (0, 15, 16, 1023, 1024, 2047):
+        for x in (0, 31, 32, 1023, 1024, 1025, 2016, 2047):
+            pts.append(y * N + x)
+    pts = np.array(pts, dtype=np.int64)
+    for prec, tol in ((pond.POND_F64, TOL64), (pond.POND_F32_MIXED, 2e-6)):
+        cfg = _cfg(w, precision=prec, max_iter=20, fixed_iter=3)
+        if prec == pond.POND_F32_MIXED:
+            cfg = cfg.replace(eps_abs=1e-6, eps_rel=1e-5)
+        st = pond.init(cfg, w.rho, w.ux, w.uy, w.T)
+        out, _ = pond.step(cfg, st)
+        fo, go, _, _ = oracle.step_nodes(st.f.double().cpu().numpy(), st.g.cpu().numpy(),
+                                         _ocfg(cfg), pts)
+        fg = out.f.double().cpu().numpy().reshape(16, -1)[:, pts]
+        gg = out.g.cpu().numpy().reshape(3, -1)[:, pts]
+        errs = state_errors(fg, gg, fo, go, u_scale=1.0, T_scale=float(np.max(w.T)))
+        assert max(errs.values()) < tol, (prec, errs)
+        del st, out
+
+
 def test_full_size_sampled_riemann_1024_adaptive(gpu):
     """The benchmark's own configuration (adaptive passes, 16-lane tail) on the
     1024^2 Riemann input: sampled nodes, including the 64 that take the most
