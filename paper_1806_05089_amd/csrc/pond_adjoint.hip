@@ -295,11 +295,17 @@ __device__ __forceinline__ void adj_window_column(const double* s_fB, double* s_
     hc[ip] = 0.0;
     hd[ip] = 0.0;
   }
+  double fnext[Q];
+  W::load(s_fB, e, eh, fnext);
 #pragma unroll
   for (int m = 0; m < 4; ++m) {
     const double aym = pick4(ay, m), daym = pick4(day, m);  // constant index once unrolled
     double fs[Q];
-    W::load(s_fB, e + m * WX * W::G, eh + m * WX * W::G, fs);
+#pragma unroll
+    for (int p = 0; p < Q; ++p) fs[p] = fnext[p];
+    // the next row's reads go out before this row's LDS atomics, which
+    // the compiler does not move reads across
+    if (m < 3) W::load(s_fB, e + (m + 1) * WX * W::G, eh + (m + 1) * WX * W::G, fnext);
     double U[Q1];
 #pragma unroll
     for (int ip = 0; ip < Q1; ++ip) {
