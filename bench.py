@@ -181,6 +181,21 @@ def adjoint_ratio_tgv128():
             "note": "backward includes the checkpoint replays (one extra forward per step)"}
 
 
+def host_cpu():
+    """The host the oracle ran on: CPU model and the threads this process may use."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": len(os.sched_getaffinity(0)),
+            "logical_cpus": os.cpu_count()}
+
+
 def cpu_baseline(cfg, state, sample_nodes, seed=0):
     import oracle
     f = state.f.double().cpu().numpy()
@@ -415,6 +430,7 @@ def main():
         achieved = flops / (ms64 / args.steps * 1e-3) / 1e12
         result["mean_pc_passes"] = passes64["mean_passes"]
         result["nonconverged_node_steps"] = passes64["nonconverged_node_steps"]
+        result["cap_hit_fraction"] = passes64["nonconverged_node_steps"] / (nodes * args.steps)
         traffic = traffic_per_launch(nodes)
         result["roofline"] = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
                               "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
@@ -465,6 +481,7 @@ def main():
         result["cpu_baseline"] = cpu_baseline(cfg64, s64, args.cpu_sample)
         result["cpu_baseline"]["single_thread"] = cpu_single_thread(cfg64, s64)
         result["cpu_baseline"]["whole_runs"] = cpu_small_configs()
+        result["cpu_baseline"]["host"] = host_cpu()
     print(json.dumps(result), flush=True)
 
 
