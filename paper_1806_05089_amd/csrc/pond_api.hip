@@ -186,14 +186,15 @@ pond::StepArgs step_args(const pond_config& c, Slot* slot) {
   a.tile_keys = slot->keys;
   a.tile_order = nullptr;
   a.tile_order_next = slot->order;
+  a.tile_cap = (unsigned)slot->cap;
   a.tape = nullptr;
   a.tape_f = nullptr;
   return a;
 }
 
 // Launches one step; the tile order left by the previous step on the stream is
-// used when it belongs to the same grid and tile shape (the tile shape depends
-// on the precision).
+// used when it belongs to the same grid and tile count (the tile shape depends
+// on the precision and the lattice).
 hipError_t launch_step_on(const pond_config& c, Slot* slot, pond::StepArgs& a, hipStream_t s) {
   const unsigned ntiles = pond::step_tile_count(c);
   const bool ordered =

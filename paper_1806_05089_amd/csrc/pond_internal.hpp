@@ -53,6 +53,9 @@ struct StepArgs {
   uint16_t* tile_keys;
   const unsigned* tile_order;
   unsigned* tile_order_next;
+  // Entries the three tile arrays hold; the kernel uses them only when its
+  // tile count fits (the tiles are then taken row-major and not keyed).
+  unsigned tile_cap;
   // Pass history for the adjoint (nullable, both or neither).  With N nodes,
   // tape[(k * 4 + c) * N + node] holds for k = 0 the seed gauge (c = 0, 1, 2:
   // u_x, u_y, T) and for k >= 1 the gauge after pass k (c = 0, 1, 2) and the

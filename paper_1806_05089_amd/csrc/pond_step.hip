@@ -549,6 +549,7 @@ k_step(StepArgs A) {
   const int tid = threadIdx.x;
   const int ntx = (A.nx + TX - 1) / TX;
   const unsigned ntiles = (unsigned)ntx * (unsigned)((A.ny + TY - 1) / TY);
+  const bool keyed = A.tile_keys && ntiles <= A.tile_cap;  // tile arrays fit this grid
   if (tid < TS::NW) s_wmax[tid] = 0u;
 
   // Persistent blocks: each block takes tiles from the queue until it is
@@ -557,7 +558,7 @@ k_step(StepArgs A) {
   for (;;) {
     if (tid == 0) {
       const unsigned g = atomicAdd(&A.queue->next, 1u);
-      s_tile = (A.tile_order && g < ntiles) ? A.tile_order[g] : g;
+      s_tile = (keyed && A.tile_order && g < ntiles) ? A.tile_order[g] : g;
     }
     if (tid < 2) s_tail[tid] = 0u;
     __syncthreads();
@@ -1128,7 +1129,7 @@ k_step(StepArgs A) {
         key += s_wmax[w];
         s_wmax[w] = 0u;
       }
-      if (A.tile_keys)
+      if (keyed)
         A.tile_keys[tile] = (uint16_t)(key < kKeyBins<NT> ? key : kKeyBins<NT> - 1);
     }
   }  // tile loop
@@ -1143,7 +1144,7 @@ k_step(StepArgs A) {
   __syncthreads();
   if (s_tile) {
     __threadfence();
-    if (A.tile_keys && A.tile_order_next)
+    if (keyed && A.tile_order_next)
       order_tiles<NT>(A.tile_keys, A.tile_order_next, ntiles, reinterpret_cast<unsigned*>(s_f));
     if (tid == 0) {
       atomicExch(&A.queue->next, 0u);
@@ -1192,16 +1193,18 @@ hipError_t launch_step_t(const StepArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <class FT>
+template <int Q1, class FT>
 unsigned tile_count_t(const pond_config& c) {
-  using ST = StepTile<4, FT>;  // both lattices use the same tile shape
+  using ST = StepTile<Q1, FT>;
   return (unsigned)(((c.nx + ST::TX - 1) / ST::TX) * (long long)((c.ny + ST::TY - 1) / ST::TY));
 }
 
 }  // namespace
 
 unsigned step_tile_count(const pond_config& c) {
-  return c.precision == POND_F64 ? tile_count_t<double>(c) : tile_count_t<float>(c);
+  if (c.q1d == 3)
+    return c.precision == POND_F64 ? tile_count_t<3, double>(c) : tile_count_t<3, float>(c);
+  return c.precision == POND_F64 ? tile_count_t<4, double>(c) : tile_count_t<4, float>(c);
 }
 
 hipError_t launch_step(const pond_config& c, const StepArgs& a, hipStream_t s) {
