@@ -973,34 +973,23 @@ k_step(StepArgs A) {
           }
         }
 
-        // a6: moments in the peculiar frame of lambda_n.  FP32-mixed sums
-        // with compensation (its tolerances sit near FP32 rounding); FP64
-        // plain fused sums (rounding ~1e-16 of the moments, far below the
-        // App. E tolerances).
-        FT r0 = 0, r0c = 0, mx = 0, mxc = 0, my = 0, myc = 0, e2 = 0, e2c = 0;
+        // a6: moments in the peculiar frame of lambda_n, summed in FP64 with
+        // fused multiply-adds in both precisions (rounding ~1e-16 of the
+        // moments, far below the App. E tolerances; FP32-mixed populations
+        // are widened exactly).
+        double r0 = 0.0, mx = 0.0, my = 0.0, e2 = 0.0;
 #pragma unroll
         for (int i = 0; i < Q1; ++i)
 #pragma unroll
           for (int j = 0; j < Q1; ++j) {
-            const FT fv = ft[i * Q1 + j];
-            const FT ci = FT(L::c(i)), cj = FT(L::c(j));
-            const FT c2 = FT(L::c(i) * L::c(i) + L::c(j) * L::c(j));
-            if constexpr (sizeof(FT) == 8) {
-              r0 += fv;
-              mx = fma(ci, fv, mx);
-              my = fma(cj, fv, my);
-              e2 = fma(c2, fv, e2);
-            } else {
-              two_sum_acc(r0, r0c, fv);
-              two_sum_acc(mx, mxc, ci * fv);
-              two_sum_acc(my, myc, cj * fv);
-              two_sum_acc(e2, e2c, c2 * fv);
-            }
+            const double fv = double(ft[i * Q1 + j]);
+            r0 += fv;
+            mx = fma(L::c(i), fv, mx);
+            my = fma(L::c(j), fv, my);
+            e2 = fma(L::c(i) * L::c(i) + L::c(j) * L::c(j), fv, e2);
           }
-        const int verdict = corrector<Q1>(A, s, ux, uy, T, double(r0) + double(r0c),
-                                          double(mx) + double(mxc), double(my) + double(myc),
-                                          double(e2) + double(e2c), passes, rho1, ux1, uy1, T1,
-                                          flags);
+        const int verdict = corrector<Q1>(A, s, ux, uy, T, r0, mx, my, e2, passes, rho1, ux1,
+                                          uy1, T1, flags);
         if (verdict == kBad) {
           bad = true;
           break;
