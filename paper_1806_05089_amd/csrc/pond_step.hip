@@ -872,9 +872,8 @@ k_step(StepArgs A) {
 #pragma unroll 1
           for (int j0 = 0; j0 < Q1; j0 += JB) {
             FT ayw[JB][4];
-            int y0[JB], ly0[JB];
+            int ly0[JB];  // first stencil row of each speed, window-relative
             bool rows_in[JB];
-            LagRow Pj[JB];
             FT gby[JB][Q1];
             FT acc_row[JB][Q1];
             bool all_in = true;
@@ -887,12 +886,10 @@ k_step(StepArgs A) {
               const double ty = yd - (fly - 1.0);
 #pragma unroll
               for (int m = 0; m < 4; ++m) ayw[b][m] = FT(interp_weight_at(m, ty));
-              y0[b] = sat_floor(fly) - 1;
-              ly0[b] = y0[b] - wy0;
+              ly0[b] = sat_floor(fly) - 1 - wy0;
               rows_in[b] = (unsigned)ly0[b] <= (unsigned)(WY - 4);
               all_in = all_in && rows_in[b];
-              Pj[b] = lag_row<Q1>(j);
-              row_to<Q1, FT>(Pj[b], rB, dBy, gby[b]);
+              row_to<Q1, FT>(lag_row<Q1>(j), rB, dBy, gby[b]);
 #pragma unroll
               for (int i = 0; i < Q1; ++i) acc_row[b][i] = FT(0);
             }
@@ -938,15 +935,16 @@ k_step(StepArgs A) {
                     const int kk = ly0[b] * WX + lx;
                     window_columns<Q1, 1, FT, WX, WN>(s_f, &kk, &ayw[b], &gby[b], &hc[b]);
                   } else {
+                    const LagRow Pj = lag_row<Q1>(j0 + b);  // (rare path: rebuilt here)
 #pragma unroll 1
                     for (int m = 0; m < 4; ++m) {
                       const FT aym = m == 0   ? ayw[b][0]
                                      : m == 1 ? ayw[b][1]
                                      : m == 2 ? ayw[b][2]
                                               : ayw[b][3];
-                      column_point<Q1, FT, WX, WY, WN>(A, s_f, wx0, wy0, X + rel, y0[b] + m, true,
-                                                       aym, wx, gby[b], Pj[b], ux, uy, inv_s, hc[b],
-                                                       acc_row[b]);
+                      column_point<Q1, FT, WX, WY, WN>(A, s_f, wx0, wy0, X + rel,
+                                                       ly0[b] + wy0 + m, true, aym, wx, gby[b],
+                                                       Pj, ux, uy, inv_s, hc[b], acc_row[b]);
                     }
                   }
                 }
