@@ -287,6 +287,15 @@ __device__ __forceinline__ void transfer_factor_deriv(double r, double d, double
 }
 
 
+// Error-free sum (Knuth TwoSum) for compensated accumulation.
+template <class R>
+__device__ __forceinline__ void two_sum_acc(R& s, R& c, R x) {
+  const R t = s + x;
+  const R bp = t - s;
+  c += (s - (t - bp)) + (x - bp);
+  s = t;
+}
+
 // LDS layout of the staged window: the Q values of a window node are kept in
 // groups of G = 16 / sizeof(FT) populations whose values are adjacent, so
 // that a group is one 16-byte LDS read.  Group g of node k starts at element

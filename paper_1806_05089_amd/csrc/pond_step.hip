@@ -971,21 +971,40 @@ k_step(StepArgs A) {
           }
         }
 
-        // a6: moments in the peculiar frame of lambda_n, summed in FP64 with
-        // fused multiply-adds in both precisions (rounding ~1e-16 of the
-        // moments, far below the App. E tolerances; FP32-mixed populations
-        // are widened exactly).
-        double r0 = 0.0, mx = 0.0, my = 0.0, e2 = 0.0;
+        // a6: moments in the peculiar frame of lambda_n.  FP64: plain fused
+        // sums (rounding ~1e-16 of the moments, far below the App. E
+        // tolerances).  FP32-mixed: FP32 accumulation with TwoSum
+        // compensation.
+        double r0, mx, my, e2;
+        if constexpr (sizeof(FT) == 8) {
+          r0 = mx = my = e2 = 0.0;
 #pragma unroll
-        for (int i = 0; i < Q1; ++i)
+          for (int i = 0; i < Q1; ++i)
 #pragma unroll
-          for (int j = 0; j < Q1; ++j) {
-            const double fv = double(ft[i * Q1 + j]);
-            r0 += fv;
-            mx = fma(L::c(i), fv, mx);
-            my = fma(L::c(j), fv, my);
-            e2 = fma(L::c(i) * L::c(i) + L::c(j) * L::c(j), fv, e2);
-          }
+            for (int j = 0; j < Q1; ++j) {
+              const double fv = ft[i * Q1 + j];
+              r0 += fv;
+              mx = fma(L::c(i), fv, mx);
+              my = fma(L::c(j), fv, my);
+              e2 = fma(L::c(i) * L::c(i) + L::c(j) * L::c(j), fv, e2);
+            }
+        } else {
+          FT a0 = 0, a0c = 0, ax = 0, axc = 0, ay = 0, ayc = 0, ae = 0, aec = 0;
+#pragma unroll
+          for (int i = 0; i < Q1; ++i)
+#pragma unroll
+            for (int j = 0; j < Q1; ++j) {
+              const FT fv = ft[i * Q1 + j];
+              two_sum_acc(a0, a0c, fv);
+              two_sum_acc(ax, axc, FT(L::c(i)) * fv);
+              two_sum_acc(ay, ayc, FT(L::c(j)) * fv);
+              two_sum_acc(ae, aec, FT(L::c(i) * L::c(i) + L::c(j) * L::c(j)) * fv);
+            }
+          r0 = double(a0) + double(a0c);
+          mx = double(ax) + double(axc);
+          my = double(ay) + double(ayc);
+          e2 = double(ae) + double(aec);
+        }
         const int verdict = corrector<Q1>(A, s, ux, uy, T, r0, mx, my, e2, passes, rho1, ux1,
                                           uy1, T1, flags);
         if (verdict == kBad) {
