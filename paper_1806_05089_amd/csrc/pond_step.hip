@@ -526,7 +526,7 @@ __device__ void order_tiles(const uint16_t* keys, unsigned* order, unsigned ntil
 }
 
 // Blocks per CU the registers are sized for: two (2 waves per SIMD, 256
-// VGPRs); FP32-mixed D2Q9 three (168 VGPRs, a few spills, measured 8-10 %
+// VGPRs); FP32-mixed D2Q9 three (168 VGPRs, 30 spilled, measured 8-10 %
 // faster than two).
 template <int Q1, class FT>
 constexpr int kStepBlocksPerCU = sizeof(FT) == 4 && Q1 == 3 ? 3 : 2;
