@@ -8,6 +8,8 @@
 * Uniform flow at Mach 0..100 stays uniform (one pass per step).
 * Mach 5 Galilean invariance, 256^2, 1000 steps FP32-mixed: the U = (5, 0)
   run equals the U = 0 run shifted by 5 n nodes.
+* The 1024^2 Riemann benchmark run, 2000 steps in both precisions: no bad
+  node at the end.
 * Adjoint rollout on the 128^2 compressible Taylor-Green vortex (Mach 0.5),
   200 steps, checkpoints every 20: gradients vs central finite differences.
 """
@@ -123,6 +125,25 @@ def test_mach5_galilean_1000_steps_fp32():
               f"{s0['mean_iters']:.2f} / {sU['mean_iters']:.2f}", flush=True)
     assert res[pond.POND_F64] < 1e-6
     assert res[pond.POND_F32_MIXED] < 2e-2
+
+
+@pytest.mark.parametrize("prec", [pond.POND_F64, pond.POND_F32_MIXED])
+def test_riemann_1024_benchmark_run_stays_physical(prec):
+    """The benchmark run in full: the 1024^2 four-quadrant Riemann problem for
+    2000 adaptive steps ends with no bad node (a bad node's NaN spreads through
+    the stencils, so the last step counts every one that ever appeared), with
+    the pass statistics of a healthy run.  Rounding changes in the moments of
+    nodes that need many passes have produced bad nodes here."""
+    w = workloads.riemann2d(1024, seed=3)
+    cfg = _cfg(w, precision=prec, max_iter=20)
+    if prec == pond.POND_F32_MIXED:
+        cfg = cfg.replace(eps_abs=1e-6, eps_rel=1e-5)
+    st = pond.init(cfg, w.rho, w.ux, w.uy, w.T)
+    out, stats = pond.step(cfg, st, nsteps=2000, stats=True)
+    print(f"prec {prec}: {stats}", flush=True)
+    assert stats["bad_state"] == 0
+    assert 1.5 < stats["mean_iters"] < 3.5 and stats["max_iters"] <= 20
+    assert torch.isfinite(out.f).all() and torch.isfinite(out.g).all()
 
 
 def test_adjoint_rollout_128_vs_finite_differences():
