@@ -279,6 +279,33 @@ def test_full_size_sampled_riemann_2048(gpu):
         del st, out
 
 
+def test_large_grid_sampled_riemann_4096(gpu):
+    """A 4096^2 grid (16.8 M nodes, 32768 tiles, 2.1 GB per FP64 population
+    buffer), beyond the benchmark sizes: FP64 with fixed passes at 256 sampled
+    nodes including the last rows and columns (index arithmetic past 2^31
+    bytes per buffer)."""
+    N = 4096
+    w = workloads.riemann2d(N, seed=3)
+    rng = np.random.default_rng(11)
+    pts = list(rng.integers(0, N * N, 224))
+    for y in (0, 2047, 4095):
+        for x in (0, 31, 2048, 4064, 4095):
+            pts.append(y * N + x)
+    pts = np.array(pts, dtype=np.int64)
+    cfg = _cfg(w, max_iter=20, fixed_iter=3)
+    st = pond.init(cfg, w.rho, w.ux, w.uy, w.T)
+    out, stats = pond.step(cfg, st, stats=True)
+    assert stats["bad_state"] == 0
+    f_in = st.f.cpu().numpy()
+    g_in = st.g.cpu().numpy()
+    del st
+    fo, go, _, _ = oracle.step_nodes(f_in, g_in, _ocfg(cfg), pts)
+    fg = out.f.cpu().numpy().reshape(16, -1)[:, pts]
+    gg = out.g.cpu().numpy().reshape(3, -1)[:, pts]
+    errs = state_errors(fg, gg, fo, go, u_scale=1.0, T_scale=float(np.max(w.T)))
+    assert max(errs.values()) < TOL64, errs
+
+
 def test_full_size_sampled_riemann_1024_adaptive(gpu):
     """The benchmark's own configuration (adaptive passes, 16-lane tail) on the
     1024^2 Riemann input: sampled nodes, including the 64 that take the most
