@@ -660,22 +660,30 @@ k_step(StepArgs A) {
       };
       if (tid < WN) fetch(tid);
       for (int k = tid; k < WN; k += NT) {
-        double f[Q];
+        FT f[Q];
 #pragma unroll
-        for (int p = 0; p < Q; ++p) f[p] = double(fn[p]);
+        for (int p = 0; p < Q; ++p) f[p] = fn[p];
         const double gux = gn[0], guy = gn[1], gT = gn[2];
         if (k + NT < WN) fetch(k + NT);
+        // the transfer factors are built in FP64 and applied in the
+        // arithmetic type (FP32-mixed: rounded, then FP32 contractions)
         const double ss = sqrt(gT * L::inv_TL);
         const double r = ss * inv_sB;
-        double Gx[Q], Gy[Q];
-        transfer_factor<Q1, double>(r, (gux - uxB) * inv_sB, Gx);
-        transfer_factor<Q1, double>(r, (guy - uyB) * inv_sB, Gy);
-        double Hm[Q];  // Hm[i][l] = sum_j Gy[l][j] f[i][j]
+        double Gxd[Q], Gyd[Q];
+        transfer_factor<Q1, double>(r, (gux - uxB) * inv_sB, Gxd);
+        transfer_factor<Q1, double>(r, (guy - uyB) * inv_sB, Gyd);
+        FT Gx[Q], Gy[Q];
+#pragma unroll
+        for (int p = 0; p < Q; ++p) {
+          Gx[p] = FT(Gxd[p]);
+          Gy[p] = FT(Gyd[p]);
+        }
+        FT Hm[Q];  // Hm[i][l] = sum_j Gy[l][j] f[i][j]
 #pragma unroll
         for (int i = 0; i < Q1; ++i)
 #pragma unroll
           for (int l = 0; l < Q1; ++l) {
-            double h = 0.0;
+            FT h = FT(0);
 #pragma unroll
             for (int j = 0; j < Q1; ++j) h = fma(Gy[l * Q1 + j], f[i * Q1 + j], h);
             Hm[i * Q1 + l] = h;
@@ -686,11 +694,11 @@ k_step(StepArgs A) {
         for (int kk = 0; kk < Q1; ++kk)
 #pragma unroll
           for (int l = 0; l < Q1; ++l) {
-            double t = 0.0;
+            FT t = FT(0);
 #pragma unroll
             for (int i = 0; i < Q1; ++i) t = fma(Gx[kk * Q1 + i], Hm[i * Q1 + l], t);
             const int p = kk * Q1 + l;
-            tv[p / W::G][p % W::G] = FT(t);
+            tv[p / W::G][p % W::G] = t;
           }
 #pragma unroll
         for (int g = 0; g < W::NG; ++g) {
