@@ -27,14 +27,15 @@
  *     pond_step_adjoint on a (device, stream) pair allocates and zeroes a small
  *     slot for it (step statistics, the step kernel's tile queue, and one cost
  *     key and one order entry per tile of 32 x 16 nodes, 32 x 8 in FP32-mixed
- *     mode, grown after a stream synchronisation when a larger grid appears);
- *     it is held until the process ends.  A step leaves its tiles' costs there, and the next step
- *     on the same stream takes the costliest tiles first; results do not
- *     depend on that order.  pond_step_adjoint also keeps its scratch there:
- *     ((K + 1) * 4 + q1d^2) * nx * ny doubles of pass history (K = fixed_iter,
- *     or max_iter in adaptive mode) and one output state, grown the same way.
- *     Calls on one stream run in order; concurrent calls on different streams
- *     use different slots.
+ *     mode: 6 bytes per tile, about 12 KiB at 1024^2, grown after a stream
+ *     synchronisation when a larger grid appears); it is held until the
+ *     process ends.  A step leaves its tiles' costs there, and the next step
+ *     on the same stream takes the costliest tiles first: a scheduling hint
+ *     only, results do not depend on that order (every call is a pure
+ *     function of its inputs).  Scratch of a size that grows with the grid
+ *     and the pass cap (the adjoint's) is the caller's: see
+ *     pond_workspace_bytes.  Calls on one stream run in order; concurrent
+ *     calls on different streams use different slots.
  *   - HIP graph capture: pond_step (without stats) and pond_step_adjoint
  *     record kernels and device copies only, no memset.  Make one call on the
  *     capturing stream before capture (it allocates the stream's slot) and
@@ -60,6 +61,7 @@ enum {
 };
 
 enum { POND_F64 = 0, POND_F32_MIXED = 1 };
+enum { POND_OP_STEP = 0, POND_OP_STEP_ADJOINT = 1 }; /* pond_workspace_bytes */
 enum { POND_PERIODIC = 0, POND_ZERO_GRADIENT = 1 };
 
 /* Bits of the per-node iteration plane written by pond_step. */
@@ -94,6 +96,10 @@ typedef struct {
   int64_t bad_state;    /* nodes with rho <= 0, T <= 0 or non-finite values      */
   int32_t max_iters;    /* largest pass count over the grid in the last step     */
   double mean_iters;    /* mean pass count per node in the last step             */
+  int64_t iter_hist[POND_ITERS_MASK + 1]; /* nodes per pass count n = 1..63 in
+                           the last step (index n; index 0 stays 0): the
+                           per-node predictor-corrector iteration counts of
+                           App. E as one histogram; sums to nx * ny          */
 } pond_stats;
 
 /*
@@ -113,13 +119,20 @@ int pond_init(const pond_config* cfg, const double* rho, const double* ux, const
  * iteration, eqs. (6)-(16) and App. E, then BGK collision, eqs. (17)-(18)).
  * `in` is the state at t - dt, `out` receives the state after nsteps steps.
  * in->f/g and out->f/g must not overlap (the semi-Lagrangian gather reads the
- * whole field at t - dt).  For nsteps > 1 the call ping-pongs between the two
- * buffers, so `in` is overwritten; with nsteps == 1 it is left intact.
+ * whole field at t - dt).  With nsteps == 1 `in` is only read.  With
+ * nsteps > 1 the call ping-pongs between the two states, so in->f and in->g
+ * are WRITTEN (they hold step nsteps - 1 or nsteps afterwards); a caller that
+ * needs them intact passes a copy.
  * out->iters (nullable) receives the pass count and status bits of the last step.
  * stats (HOST pointer, nullable): if given, filled for the last step; the call
  * then synchronises the stream before returning.
+ * In POND_F32_MIXED mode with adaptive passes (fixed_iter == 0) the App. E
+ * tolerances must be reachable in FP32: max(eps_abs, eps_rel) below 2^-23
+ * (FP32 machine epsilon) is rejected with POND_E_INVALID (the paper's FP64
+ * values 1e-12 / 1e-10 would run every node to max_iter); the same holds for
+ * pond_step_record and both adjoint calls.
  */
-int pond_step(const pond_config* cfg, const pond_state* in, pond_state* out, int32_t nsteps,
+int pond_step(const pond_config* cfg, pond_state* in, pond_state* out, int32_t nsteps,
               void* hip_stream, pond_stats* stats);
 
 /*
@@ -132,21 +145,49 @@ int pond_moments(const pond_config* cfg, const pond_state* state, double* rho, d
                  double* uy, double* T, double* Mmn, void* hip_stream);
 
 /*
+ * Caller workspace for an operation, written to *bytes (host pointer):
+ *   POND_OP_STEP          0 (pond_step needs none beyond the stream slot);
+ *   POND_OP_STEP_ADJOINT  the pass history of one step plus one output
+ *                         state: ((K + 1) * 4 + q1d^2) * nx * ny * 8 bytes
+ *                         (K = fixed_iter, or max_iter in adaptive mode),
+ *                         + f, g and iters of one state, each part rounded up
+ *                         to 256 bytes.
+ * POND_E_INVALID for another op.
+ */
+int pond_workspace_bytes(const pond_config* cfg, int32_t op, int64_t* bytes);
+
+/*
  * Vector-Jacobian product of one pond_step (nsteps = 1) about the forward pass
  * in -> out_fwd, the unrolled predictor-corrector iteration differentiated
- * with its pass counts fixed (the computed map).  The call first runs that
- * step again from `in` with the same configuration, recording every node's
- * pass gauges, densities and last-pass populations in the stream's scratch
- * (the step is deterministic, so this run reproduces out_fwd bit for bit),
- * then the adjoint kernel.  out_fwd is the caller's forward result; it must be
- * given (with iters) but is not read.
+ * with its pass counts fixed (the computed map; eqs. (4)-(18) taken
+ * backwards).  The call first runs that step again from `in` with the same
+ * configuration, recording every node's pass gauges, densities and last-pass
+ * populations in the caller's workspace (the step is deterministic, so this
+ * run reproduces out_fwd bit for bit), then the adjoint kernel.  out_fwd is
+ * the caller's forward result; it must be given (with iters) but is not read.
  * adj_out: cotangents of (f, g) at t (adj_out->f is double in both precisions).
  * adj_in:  receives the cotangents of (f, g) at t - dt (double); it is
  *          overwritten, not accumulated.  Must not overlap the other buffers.
  * adj_tau (device double*, nullable): d/dtau of <adj_out, out> is ADDED to it.
+ * workspace: device memory owned by the caller, 16-byte aligned, at least
+ *          pond_workspace_bytes(cfg, POND_OP_STEP_ADJOINT) bytes
+ *          (workspace_bytes gives its size; smaller: POND_E_INVALID); it must
+ *          not overlap the other buffers (POND_E_ALIAS) and is scratch only:
+ *          its contents are undefined after the call.
  */
 int pond_step_adjoint(const pond_config* cfg, const pond_state* in, const pond_state* out_fwd,
                       const pond_state* adj_out, pond_state* adj_in, double* adj_tau,
+                      void* workspace, int64_t workspace_bytes, void* hip_stream);
+
+/*
+ * Transpose of pond_init (the equilibrium f_p = rho W_p of eq. (17), in the
+ * gauge {u, T}): from cotangents adj_f [q1d^2][ny][nx] and adj_g [3][ny][nx]
+ * (double device arrays), adj_rho = sum_p W_p adj_f_p and adj_ux, adj_uy,
+ * adj_T = the three planes of adj_g ([ny][nx] double device arrays, each
+ * nullable, overwritten; they must not overlap adj_f or adj_g).
+ */
+int pond_init_adjoint(const pond_config* cfg, const double* adj_f, const double* adj_g,
+                      double* adj_rho, double* adj_ux, double* adj_uy, double* adj_T,
                       void* hip_stream);
 
 /*
@@ -182,8 +223,10 @@ int pond_step_adjoint_recorded(const pond_config* cfg, const pond_state* in,
 /* Message for the last nonzero return on this thread ("" if none). */
 const char* pond_last_error(void);
 
-/* ABI version of this header (major * 100 + minor): 101 adds the recorded
- * steps (pond_tape_bytes, pond_step_record, pond_step_adjoint_recorded). */
+/* ABI version of this header (major * 100 + minor).  101 added the recorded
+ * steps (pond_tape_bytes, pond_step_record, pond_step_adjoint_recorded); 200:
+ * the pass histogram in pond_stats, pond_step_adjoint on caller workspace
+ * (pond_workspace_bytes), pond_init_adjoint, `in` of pond_step not const. */
 int pond_abi_version(void);
 
 #ifdef __cplusplus

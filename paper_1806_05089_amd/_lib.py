@@ -17,6 +17,8 @@ POND_E_UNSUPPORTED = -6
 
 POND_F64 = 0
 POND_F32_MIXED = 1
+POND_OP_STEP = 0
+POND_OP_STEP_ADJOINT = 1
 POND_PERIODIC = 0
 POND_ZERO_GRADIENT = 1
 
@@ -26,7 +28,7 @@ POND_ITERS_BAD = 0x80
 
 EXPORTED = ("pond_init", "pond_step", "pond_moments", "pond_step_adjoint", "pond_last_error",
             "pond_abi_version", "pond_tape_bytes", "pond_step_record",
-            "pond_step_adjoint_recorded")
+            "pond_step_adjoint_recorded", "pond_workspace_bytes", "pond_init_adjoint")
 
 
 class pond_config(C.Structure):
@@ -43,7 +45,7 @@ class pond_state(C.Structure):
 
 class pond_stats(C.Structure):
     _fields_ = [("nonconverged", C.c_int64), ("bad_state", C.c_int64), ("max_iters", C.c_int32),
-                ("mean_iters", C.c_double)]
+                ("mean_iters", C.c_double), ("iter_hist", C.c_int64 * (POND_ITERS_MASK + 1))]
 
 
 class PondError(RuntimeError):
@@ -76,7 +78,7 @@ def load(path: str | None = None):
     lib.pond_step.restype = C.c_int
     lib.pond_moments.argtypes = [cp, sp, dp, dp, dp, dp, dp, dp]
     lib.pond_moments.restype = C.c_int
-    lib.pond_step_adjoint.argtypes = [cp, sp, sp, sp, sp, dp, dp]
+    lib.pond_step_adjoint.argtypes = [cp, sp, sp, sp, sp, dp, dp, C.c_int64, dp]
     lib.pond_step_adjoint.restype = C.c_int
     lib.pond_tape_bytes.argtypes = [cp, C.POINTER(C.c_int64)]
     lib.pond_tape_bytes.restype = C.c_int
@@ -84,6 +86,10 @@ def load(path: str | None = None):
     lib.pond_step_record.restype = C.c_int
     lib.pond_step_adjoint_recorded.argtypes = [cp, sp, sp, dp, sp, sp, dp, dp]
     lib.pond_step_adjoint_recorded.restype = C.c_int
+    lib.pond_workspace_bytes.argtypes = [cp, C.c_int32, C.POINTER(C.c_int64)]
+    lib.pond_workspace_bytes.restype = C.c_int
+    lib.pond_init_adjoint.argtypes = [cp, dp, dp, dp, dp, dp, dp, dp]
+    lib.pond_init_adjoint.restype = C.c_int
     lib.pond_last_error.argtypes = []
     lib.pond_last_error.restype = C.c_char_p
     lib.pond_abi_version.argtypes = []

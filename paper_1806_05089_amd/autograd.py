@@ -10,9 +10,10 @@ initial populations and gauge and to tau (nu = T_ref (tau - 1/2) dt, so
 dJ/dnu = (dJ/dtau) / T_ref).
 
 ``equilibrium_state`` builds the initial state from macroscopic fields with
-the same kernel as pond_init and gives the fields their gradients; the
-equilibrium f = rho W_i W_j is linear in rho, so its transpose is a weighted
-sum over populations.
+pond_init and gives the fields their gradients with pond_init_adjoint (the
+equilibrium f = rho W_i W_j is linear in rho; its transpose is the W-weighted
+sum over populations, computed in the library).  ``kinetic_energy`` takes the
+density from pond_moments.
 """
 from __future__ import annotations
 
@@ -22,32 +23,23 @@ from . import pond
 from .pond import PondConfig, PondState
 
 
-def _weights(cfg: PondConfig, device) -> torch.Tensor:
-    """rho -> f map of the equilibrium initial state, read back from pond_init."""
-    one = torch.ones((1, 1), dtype=torch.float64)
-    zero = torch.zeros((1, 1), dtype=torch.float64)
-    c1 = cfg.replace(nx=1, ny=1, precision=pond.POND_F64)
-    T = one if cfg.q1d == 4 else one / 3.0
-    st = pond.init(c1, one, zero, zero, T, device=device)
-    return st.f.reshape(cfg.Q)
-
-
 class _Equilibrium(torch.autograd.Function):
     @staticmethod
     def forward(ctx, rho, ux, uy, T, cfg: PondConfig):
         st = pond.init(cfg, rho.detach(), ux.detach(), uy.detach(), T.detach(), device=rho.device)
         ctx.cfg = cfg
-        ctx.save_for_backward(_weights(cfg, rho.device))
         return st.f, st.g
 
     @staticmethod
     def backward(ctx, gf, gg):
-        (W,) = ctx.saved_tensors
-        grho = gux = guy = gT = None
-        if gf is not None:
-            grho = torch.einsum("p,pyx->yx", W, gf.double())
-        if gg is not None:
-            gux, guy, gT = gg[0], gg[1], gg[2]
+        cfg = ctx.cfg
+        af = gf.double().contiguous() if gf is not None else None
+        ag = gg.double().contiguous() if gg is not None else None
+        if af is None:
+            af = torch.zeros((cfg.Q, cfg.ny, cfg.nx), dtype=torch.float64, device=ag.device)
+        if ag is None:
+            ag = torch.zeros((3, cfg.ny, cfg.nx), dtype=torch.float64, device=af.device)
+        grho, gux, guy, gT = pond.init_adjoint(cfg, af, ag)
         return grho, gux, guy, gT, None
 
 
@@ -105,7 +97,31 @@ def rollout(f0, g0, tau, cfg: PondConfig, nsteps: int, checkpoint_every: int = 2
     return PondRollout.apply(f0, g0, tau, cfg, nsteps, checkpoint_every)
 
 
+class _Density(torch.autograd.Function):
+    """rho = sum_p f_p (eq. (10)) from pond_moments; its transpose hands the
+    cotangent of rho to every population unchanged."""
+
+    @staticmethod
+    def forward(ctx, f, g):
+        Q, ny, nx = f.shape
+        cfg = PondConfig(nx=nx, ny=ny, q1d=4 if Q == 16 else 3,
+                         precision=pond.POND_F64 if f.dtype == torch.float64 else pond.POND_F32_MIXED)
+        st = PondState(f.detach().contiguous(), g.detach().contiguous(), None)
+        ctx.shape = f.shape
+        ctx.dtype = f.dtype
+        return pond.moments(cfg, st)[0]
+
+    @staticmethod
+    def backward(ctx, grho):
+        return grho.to(ctx.dtype).expand(ctx.shape).contiguous(), None
+
+
+def density(f, g):
+    """rho of a state (pond_moments), differentiable in f."""
+    return _Density.apply(f, g)
+
+
 def kinetic_energy(f, g):
     """J = sum over nodes of rho |u|^2 / 2 with rho = sum_p f_p and u the node gauge."""
-    rho = f.double().sum(0)
+    rho = density(f, g)
     return 0.5 * (rho * (g[0] * g[0] + g[1] * g[1])).sum()

@@ -1,6 +1,7 @@
 // C ABI of libpond: argument checks, buffer ping-pong and kernel launches.
 #include <hip/hip_runtime.h>
 
+#include <cstdint>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -26,12 +27,11 @@ int hip_fail(hipError_t e, const char* where) {
 }
 
 // Device memory kept per (device, stream): step statistics, the step
-// kernel's tile queue, the tile cost keys and tile order that one step leaves
-// for the next, and the adjoint's scratch (the pass history of the step it
-// differentiates and that step's output state).  Work on one stream runs in
-// order, so a slot is never used by two kernels at once.  Allocated on the
-// first call on a stream (the arrays grow with the grid) and held until the
-// process ends.
+// kernel's tile queue, and the tile cost keys and tile order that one step
+// leaves for the next (a scheduling hint: results do not depend on it).  Work
+// on one stream runs in order, so a slot is never used by two kernels at
+// once.  Allocated on the first call on a stream (the arrays grow with the
+// grid) and held until the process ends.
 struct Slot {
   pond::StreamSlot* dev = nullptr;
   uint16_t* keys = nullptr;
@@ -40,8 +40,6 @@ struct Slot {
   int order_nx = -1;        // grid and tile count whose tile order `order` holds
   int order_ny = -1;
   unsigned order_tiles = 0;
-  void* adj_mem = nullptr;  // adjoint scratch, adj_cap bytes
-  size_t adj_cap = 0;
 };
 std::mutex g_mutex;
 std::map<std::pair<int, void*>, Slot> g_slots;
@@ -94,26 +92,6 @@ int ensure_tile_arrays(Slot* sl, size_t ntiles, hipStream_t s) {
   return POND_OK;
 }
 
-// Adjoint scratch of `bytes` bytes.  Growing it waits for the stream, since a
-// kernel in flight may still use the old memory.
-int ensure_adjoint_scratch(Slot* sl, size_t bytes, hipStream_t s) {
-  if (sl->adj_cap >= bytes) return POND_OK;
-  hipError_t e;
-  if (sl->adj_cap) {
-    if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "pond_step_adjoint sync");
-    (void)hipFree(sl->adj_mem);
-    sl->adj_mem = nullptr;
-    sl->adj_cap = 0;
-  }
-  e = hipMalloc(&sl->adj_mem, bytes);
-  if (e != hipSuccess) {
-    sl->adj_mem = nullptr;
-    return hip_fail(e, "hipMalloc(adjoint scratch)");
-  }
-  sl->adj_cap = bytes;
-  return POND_OK;
-}
-
 // Passes a node runs one lane per node before an unconverged node moves to the
 // block's 16-lane tail (POND_BULK_CAP overrides the default).
 int bulk_cap(int precision) {
@@ -157,6 +135,19 @@ int check_config(const pond_config* c) {
   if (!(c->tau > 0.0) || !(c->tau < 1e30)) return fail(POND_E_INVALID, "tau must be finite and > 0");
   if (!(c->eps_abs >= 0.0) || !(c->eps_rel >= 0.0))
     return fail(POND_E_INVALID, "eps_abs and eps_rel must be >= 0");
+  return POND_OK;
+}
+
+// Calls that run the step: in FP32-mixed mode with adaptive passes the App. E
+// tolerances must be reachable in FP32 (the FP64 defaults would run every
+// node to max_iter).
+int check_step_tolerances(const pond_config* c, const char* who) {
+  constexpr double kEpsF32 = 1.1920928955078125e-07;  // 2^-23
+  if (c->precision == POND_F32_MIXED && c->fixed_iter == 0 &&
+      !(c->eps_abs >= kEpsF32 || c->eps_rel >= kEpsF32))
+    return fail(POND_E_INVALID, std::string(who) +
+                                    ": FP32-mixed adaptive passes need max(eps_abs, eps_rel) >= "
+                                    "2^-23 (FP32 resolution), e.g. 1e-6 / 1e-5");
   return POND_OK;
 }
 
@@ -227,6 +218,21 @@ TapeLayout tape_layout(const pond_config& c) {
   return t;
 }
 
+// Caller workspace of pond_step_adjoint: the recorded step's pass history,
+// then its output state (f, g, iters), each part aligned to 256 bytes.
+struct AdjointWorkspace {
+  size_t f_offset, g_offset, iters_offset, total;  // bytes
+};
+AdjointWorkspace adjoint_workspace(const pond_config& c) {
+  auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+  AdjointWorkspace w;
+  w.f_offset = up(tape_layout(c).total);
+  w.g_offset = w.f_offset + up(f_bytes(c));
+  w.iters_offset = w.g_offset + up(g_bytes(c));
+  w.total = w.iters_offset + up((size_t)c.nx * c.ny);
+  return w;
+}
+
 // One step from (in_f, in_g) with its pass history written to `tape`.
 hipError_t record_step(const pond_config& c, Slot* slot, const void* in_f, const double* in_g,
                        void* out_f, double* out_g, uint8_t* out_iters, char* tape,
@@ -277,7 +283,7 @@ extern "C" {
 
 const char* pond_last_error(void) { return g_last_error.c_str(); }
 
-int pond_abi_version(void) { return 101; }
+int pond_abi_version(void) { return 200; }
 
 int pond_init(const pond_config* cfg, const double* rho, const double* ux, const double* uy,
               const double* T, pond_state* out, void* hip_stream) {
@@ -307,11 +313,12 @@ int pond_init(const pond_config* cfg, const double* rho, const double* ux, const
   return POND_OK;
 }
 
-int pond_step(const pond_config* cfg, const pond_state* in, pond_state* out, int32_t nsteps,
+int pond_step(const pond_config* cfg, pond_state* in, pond_state* out, int32_t nsteps,
               void* hip_stream, pond_stats* stats) {
   g_last_error.clear();
   int rc = check_config(cfg);
   if (rc) return rc;
+  if ((rc = check_step_tolerances(cfg, "pond_step"))) return rc;
   if (!in || !out || !in->f || !in->g || !out->f || !out->g)
     return fail(POND_E_NULL, "pond_step: a state buffer is NULL");
   if (nsteps < 1) return fail(POND_E_INVALID, "pond_step: nsteps must be >= 1");
@@ -342,7 +349,8 @@ int pond_step(const pond_config* cfg, const pond_state* in, pond_state* out, int
     a.g_out = dst_g;
     a.counters = (last && cnt) ? cnt : nullptr;
     if (a.counters) {
-      e = pond::launch_zero_u64(reinterpret_cast<unsigned long long*>(cnt), 4, s);
+      e = pond::launch_zero_u64(reinterpret_cast<unsigned long long*>(cnt),
+                                pond::kStepCounterWords, s);
       if (e != hipSuccess) return hip_fail(e, "pond_step zero counters");
     }
     e = launch_step_on(*cfg, slot, a, s);
@@ -365,6 +373,7 @@ int pond_step(const pond_config* cfg, const pond_state* in, pond_state* out, int
     stats->bad_state = (int64_t)h.bad;
     stats->max_iters = (int32_t)h.max_passes;
     stats->mean_iters = (double)h.sum_passes / ((double)cfg->nx * cfg->ny);
+    for (int k = 0; k <= POND_ITERS_MASK; ++k) stats->iter_hist[k] = (int64_t)h.hist[k];
   }
   return POND_OK;
 }
@@ -395,6 +404,7 @@ int pond_step_record(const pond_config* cfg, const pond_state* in, pond_state* o
   g_last_error.clear();
   int rc = check_config(cfg);
   if (rc) return rc;
+  if ((rc = check_step_tolerances(cfg, "pond_step_record"))) return rc;
   if (!in || !out || !in->f || !in->g || !out->f || !out->g || !out->iters || !tape)
     return fail(POND_E_NULL, "pond_step_record: a required buffer is NULL");
   const size_t fb = f_bytes(*cfg), gb = g_bytes(*cfg), plane = (size_t)cfg->nx * cfg->ny;
@@ -422,6 +432,7 @@ int pond_step_adjoint_recorded(const pond_config* cfg, const pond_state* in,
   g_last_error.clear();
   int rc = check_config(cfg);
   if (rc) return rc;
+  if ((rc = check_step_tolerances(cfg, "pond_step_adjoint_recorded"))) return rc;
   if (!in || !out_fwd || !tape || !adj_out || !adj_in || !in->f || !in->g || !out_fwd->iters ||
       !adj_out->f || !adj_out->g || !adj_in->f || !adj_in->g)
     return fail(POND_E_NULL, "pond_step_adjoint_recorded: a required buffer is NULL");
@@ -433,35 +444,77 @@ int pond_step_adjoint_recorded(const pond_config* cfg, const pond_state* in,
                            adj_out, adj_in, adj_tau, s);
 }
 
-int pond_step_adjoint(const pond_config* cfg, const pond_state* in, const pond_state* out_fwd,
-                      const pond_state* adj_out, pond_state* adj_in, double* adj_tau,
-                      void* hip_stream) {
+int pond_workspace_bytes(const pond_config* cfg, int32_t op, int64_t* bytes) {
   g_last_error.clear();
   int rc = check_config(cfg);
   if (rc) return rc;
+  if (!bytes) return fail(POND_E_NULL, "pond_workspace_bytes: bytes is NULL");
+  if (op == POND_OP_STEP) {
+    *bytes = 0;
+  } else if (op == POND_OP_STEP_ADJOINT) {
+    *bytes = (int64_t)adjoint_workspace(*cfg).total;
+  } else {
+    return fail(POND_E_INVALID, "pond_workspace_bytes: op must be POND_OP_STEP or POND_OP_STEP_ADJOINT");
+  }
+  return POND_OK;
+}
+
+int pond_step_adjoint(const pond_config* cfg, const pond_state* in, const pond_state* out_fwd,
+                      const pond_state* adj_out, pond_state* adj_in, double* adj_tau,
+                      void* workspace, int64_t workspace_bytes, void* hip_stream) {
+  g_last_error.clear();
+  int rc = check_config(cfg);
+  if (rc) return rc;
+  if ((rc = check_step_tolerances(cfg, "pond_step_adjoint"))) return rc;
   if (!in || !out_fwd || !adj_out || !adj_in || !in->f || !in->g || !out_fwd->iters ||
-      !adj_out->f || !adj_out->g || !adj_in->f || !adj_in->g)
+      !adj_out->f || !adj_out->g || !adj_in->f || !adj_in->g || !workspace)
     return fail(POND_E_NULL, "pond_step_adjoint: a required buffer is NULL");
+  const AdjointWorkspace w = adjoint_workspace(*cfg);
+  if (workspace_bytes < 0 || (size_t)workspace_bytes < w.total)
+    return fail(POND_E_INVALID, "pond_step_adjoint: workspace smaller than "
+                                "pond_workspace_bytes(cfg, POND_OP_STEP_ADJOINT)");
+  if (reinterpret_cast<uintptr_t>(workspace) % 16 != 0)
+    return fail(POND_E_INVALID, "pond_step_adjoint: workspace must be 16-byte aligned");
   if ((rc = check_adjoint_aliasing(*cfg, in, adj_out, adj_in, nullptr))) return rc;
+  const size_t fb = f_bytes(*cfg), gb = g_bytes(*cfg);
+  const size_t afb = (size_t)cfg->nx * cfg->ny * cfg->q1d * cfg->q1d * sizeof(double);
+  if (overlap(workspace, w.total, in->f, fb) || overlap(workspace, w.total, in->g, gb) ||
+      overlap(workspace, w.total, adj_out->f, afb) || overlap(workspace, w.total, adj_out->g, gb) ||
+      overlap(workspace, w.total, adj_in->f, afb) || overlap(workspace, w.total, adj_in->g, gb))
+    return fail(POND_E_ALIAS, "pond_step_adjoint: workspace overlaps another buffer");
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   Slot* slot = nullptr;
   if ((rc = slot_for_stream(s, &slot))) return rc;
   if ((rc = ensure_tile_arrays(slot, pond::step_tile_count(*cfg), s))) return rc;
   // The step is run again with its pass history recorded (it reproduces
-  // out_fwd bit for bit) into the stream's scratch: tape, output state.
-  const size_t plane = (size_t)cfg->nx * cfg->ny;
-  const size_t fb = f_bytes(*cfg), gb = g_bytes(*cfg);
-  const size_t align = 256;
-  auto up = [&](size_t b) { return (b + align - 1) / align * align; };
-  const size_t tb = up(tape_layout(*cfg).total);
-  if ((rc = ensure_adjoint_scratch(slot, tb + up(fb) + up(gb) + up(plane), s))) return rc;
-  char* m = static_cast<char*>(slot->adj_mem);
-  void* sf = m + tb;
-  double* sg = reinterpret_cast<double*>(m + tb + up(fb));
-  uint8_t* siters = reinterpret_cast<uint8_t*>(m + tb + up(fb) + up(gb));
+  // out_fwd bit for bit) into the caller's workspace: tape, output state.
+  char* m = static_cast<char*>(workspace);
+  void* sf = m + w.f_offset;
+  double* sg = reinterpret_cast<double*>(m + w.g_offset);
+  uint8_t* siters = reinterpret_cast<uint8_t*>(m + w.iters_offset);
   const hipError_t e = record_step(*cfg, slot, in->f, in->g, sf, sg, siters, m, s);
   if (e != hipSuccess) return hip_fail(e, "pond_step_adjoint step launch");
   return launch_adjoint_on(*cfg, slot, in, siters, m, adj_out, adj_in, adj_tau, s);
+}
+
+int pond_init_adjoint(const pond_config* cfg, const double* adj_f, const double* adj_g,
+                      double* adj_rho, double* adj_ux, double* adj_uy, double* adj_T,
+                      void* hip_stream) {
+  g_last_error.clear();
+  int rc = check_config(cfg);
+  if (rc) return rc;
+  if (!adj_f || !adj_g) return fail(POND_E_NULL, "pond_init_adjoint: adj_f or adj_g is NULL");
+  const size_t plane = (size_t)cfg->nx * cfg->ny;
+  const size_t afb = plane * cfg->q1d * cfg->q1d * sizeof(double), agb = g_bytes(*cfg);
+  double* outs[4] = {adj_rho, adj_ux, adj_uy, adj_T};
+  for (double* o : outs)
+    if (o && (overlap(o, plane * sizeof(double), adj_f, afb) ||
+              overlap(o, plane * sizeof(double), adj_g, agb)))
+      return fail(POND_E_ALIAS, "pond_init_adjoint: an output overlaps adj_f or adj_g");
+  const hipError_t e = pond::launch_init_adjoint(*cfg, adj_f, adj_g, adj_rho, adj_ux, adj_uy,
+                                                 adj_T, static_cast<hipStream_t>(hip_stream));
+  if (e != hipSuccess) return hip_fail(e, "pond_init_adjoint launch");
+  return POND_OK;
 }
 
 }  // extern "C"

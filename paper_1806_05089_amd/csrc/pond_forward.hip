@@ -96,6 +96,32 @@ k_moments(int nx, int ny, const FT* __restrict__ f, const double* __restrict__ g
   }
 }
 
+// ------------------------------------------------ transpose of the init
+// f_p = rho W_p (eq. (17)) is linear in rho and does not depend on the gauge
+// (the populations live in the node's own gauge), so the cotangent of rho is
+// the W-weighted sum of the population cotangents and the gauge cotangents
+// are those of g.
+template <int Q1>
+__global__ void __launch_bounds__(256)
+k_init_adjoint(size_t plane, const double* __restrict__ adj_f, const double* __restrict__ adj_g,
+               double* __restrict__ adj_rho, double* __restrict__ adj_ux,
+               double* __restrict__ adj_uy, double* __restrict__ adj_T) {
+  const size_t node = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (node >= plane) return;
+  if (adj_rho) {
+    double a = 0.0;
+#pragma unroll
+    for (int i = 0; i < Q1; ++i)
+#pragma unroll
+      for (int j = 0; j < Q1; ++j)
+        a = fma(Lat<Q1>::w(i) * Lat<Q1>::w(j), adj_f[(size_t)(i * Q1 + j) * plane + node], a);
+    adj_rho[node] = a;
+  }
+  if (adj_ux) adj_ux[node] = adj_g[node];
+  if (adj_uy) adj_uy[node] = adj_g[plane + node];
+  if (adj_T) adj_T[node] = adj_g[2 * plane + node];
+}
+
 __global__ void k_zero_u64(unsigned long long* p, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0ull;
@@ -121,6 +147,20 @@ hipError_t launch_init(const pond_config& c, const double* rho, const double* ux
     if (f64) hipLaunchKernelGGL((k_init<3, double>), grid, block, 0, s, c.nx, c.ny, rho, ux, uy, T, (double*)f, g, iters, bad_count);
     else hipLaunchKernelGGL((k_init<3, float>), grid, block, 0, s, c.nx, c.ny, rho, ux, uy, T, (float*)f, g, iters, bad_count);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_init_adjoint(const pond_config& c, const double* adj_f, const double* adj_g,
+                               double* adj_rho, double* adj_ux, double* adj_uy, double* adj_T,
+                               hipStream_t s) {
+  const size_t plane = (size_t)c.nx * c.ny;
+  dim3 block(256), grid((unsigned)((plane + 255) / 256));
+  if (c.q1d == 4)
+    hipLaunchKernelGGL((k_init_adjoint<4>), grid, block, 0, s, plane, adj_f, adj_g, adj_rho,
+                       adj_ux, adj_uy, adj_T);
+  else
+    hipLaunchKernelGGL((k_init_adjoint<3>), grid, block, 0, s, plane, adj_f, adj_g, adj_rho,
+                       adj_ux, adj_uy, adj_T);
   return hipGetLastError();
 }
 

@@ -8,13 +8,16 @@
 
 namespace pond {
 
-// Device counters of one step (reset before the step by a fill kernel).
+// Device counters of one step (reset before the step by a fill kernel):
+// totals, then the number of nodes per pass count (index = passes, 0..63).
 struct StepCounters {
   unsigned long long nonconverged;
   unsigned long long bad;
   unsigned long long sum_passes;
   unsigned long long max_passes;
+  unsigned long long hist[POND_ITERS_MASK + 1];
 };
+constexpr int kStepCounterWords = (int)(sizeof(StepCounters) / sizeof(unsigned long long));
 
 // Tile queue of the persistent step kernel: blocks take tiles in order from
 // `next`; the last block to finish resets both fields to zero, so the queue is
@@ -74,6 +77,11 @@ unsigned step_tile_count(const pond_config& c);
 hipError_t launch_moments(const pond_config& c, const void* f, const double* g, double* rho,
                           double* ux, double* uy, double* T, double* Mmn, hipStream_t s);
 hipError_t launch_zero_u64(unsigned long long* p, int n, hipStream_t s);
+// Transpose of the equilibrium initialisation (eq. (17)): adj_rho = sum_p W_p
+// adj_f_p, the gauge cotangents pass through.  Every output is nullable.
+hipError_t launch_init_adjoint(const pond_config& c, const double* adj_f, const double* adj_g,
+                               double* adj_rho, double* adj_ux, double* adj_uy, double* adj_T,
+                               hipStream_t s);
 // Adjoint of one step; iters, tape and tape_f are the pass counts and the
 // pass history that a step with the same input and configuration recorded
 // (tape_slots gauge slots per node: nodes with more passes get no derivative).

@@ -329,14 +329,15 @@ __device__ __forceinline__ void store_bad(const StepArgs& A, FT* fout, size_t pl
 // this together (the shuffles span the wave); lanes of a group without a node
 // pass has = false.  Collocation points come from the block's LDS window
 // (pair_value, HBM outside it).  The group's final pass count raises *s_key,
-// the pass maximum of the wave that deferred the node.
+// the pass maximum of the wave that deferred the node, and, when the step
+// keeps statistics, its bin of the block's pass histogram s_hist.
 template <int Q1, class FT, int WX, int WY, int WN>
 __device__ __forceinline__ void tail_group(const StepArgs& A, const FT* s_f, int wx0, int wy0,
                                            double uxB, double uyB, double sB, bool has, int X,
                                            int Y, double ux, double uy, double T, unsigned passes,
-                                           unsigned* s_key, unsigned long long& c_nc,
-                                           unsigned long long& c_nb, unsigned long long& c_sp,
-                                           unsigned long long& c_mp) {
+                                           unsigned* s_key, unsigned* s_hist,
+                                           unsigned long long& c_nc, unsigned long long& c_nb,
+                                           unsigned long long& c_sp, unsigned long long& c_mp) {
   constexpr int Q = Q1 * Q1;
   using L = Lat<Q1>;
   const size_t plane = (size_t)A.nx * A.ny;
@@ -483,6 +484,7 @@ __device__ __forceinline__ void tail_group(const StepArgs& A, const FT* s_f, int
     if (p == 0) {
       if (A.iters) A.iters[node] = (uint8_t)((passes & POND_ITERS_MASK) | flags);
       atomicMax(s_key, passes);
+      if (A.counters) atomicAdd(&s_hist[passes & POND_ITERS_MASK], 1u);
       c_nc += (flags & POND_ITERS_NONCONVERGED) ? 1 : 0;
       c_nb += (flags & POND_ITERS_BAD) ? 1 : 0;
       c_sp += passes;
@@ -544,13 +546,16 @@ k_step(StepArgs A) {
   __shared__ unsigned s_list[NT];  // deferred nodes: local index | passes << 16
   __shared__ unsigned s_tail[2];   // list length, next entry to take
   __shared__ unsigned s_tile;
+  __shared__ unsigned s_last;          // this block is the last one out
   __shared__ unsigned s_wmax[TS::NW];  // per wave: maximum passes of its nodes
+  __shared__ unsigned s_hist[POND_ITERS_MASK + 1];  // nodes per pass count (statistics)
 
   const int tid = threadIdx.x;
   const int ntx = (A.nx + TX - 1) / TX;
   const unsigned ntiles = (unsigned)ntx * (unsigned)((A.ny + TY - 1) / TY);
   const bool keyed = A.tile_keys && ntiles <= A.tile_cap;  // tile arrays fit this grid
   if (tid < TS::NW) s_wmax[tid] = 0u;
+  if (tid <= POND_ITERS_MASK) s_hist[tid] = 0u;
 
   // Persistent blocks: each block takes tiles from the queue until it is
   // empty, so the cost spread between tiles (passes cluster along fronts) is
@@ -1078,6 +1083,7 @@ k_step(StepArgs A) {
           A.g_out[2 * plane + node] = T1;
         }
         if (A.iters) A.iters[node] = (uint8_t)((passes & POND_ITERS_MASK) | flags);
+        if (A.counters) atomicAdd(&s_hist[passes & POND_ITERS_MASK], 1u);
         c_nc += (flags & POND_ITERS_NONCONVERGED) ? 1 : 0;
         c_nb += (flags & POND_ITERS_BAD) ? 1 : 0;
         c_sp += passes;
@@ -1127,7 +1133,7 @@ k_step(StepArgs A) {
                                    __HIP_MEMORY_SCOPE_AGENT);
           }
           tail_group<Q1, FT, WX, WY, WN>(A, s_f, wx0, wy0, uxB, uyB, sB, has, tX, tY, tux, tuy, tT,
-                                         ent >> 16, &s_wmax[lw], c_nc, c_nb, c_sp, c_mp);
+                                         ent >> 16, &s_wmax[lw], s_hist, c_nc, c_nb, c_sp, c_mp);
         }
       }
     }
@@ -1160,15 +1166,21 @@ k_step(StepArgs A) {
     }
   }  // tile loop
 
+  // The block's pass histogram is complete: its last updates precede the
+  // barriers of the final loop iteration.
+  if (A.counters && tid <= POND_ITERS_MASK && s_hist[tid])
+    atomicAdd(&A.counters->hist[tid], (unsigned long long)s_hist[tid]);
+
   // The last block out orders the tiles for the next launch by this step's
   // keys and resets the queue.  Every block has taken its last tile before it
-  // counts itself out, so the order array is no longer read.
+  // counts itself out, so the order array is no longer read.  The flag has an
+  // LDS word of its own: a wave still about to read s_tile must not see it.
   if (tid == 0) {
     __threadfence();
-    s_tile = atomicAdd(&A.queue->done, 1u) == gridDim.x - 1 ? 1u : 0u;
+    s_last = atomicAdd(&A.queue->done, 1u) == gridDim.x - 1 ? 1u : 0u;
   }
   __syncthreads();
-  if (s_tile) {
+  if (s_last) {
     __threadfence();
     if (keyed && A.tile_order_next)
       order_tiles<NT>(A.tile_keys, A.tile_order_next, ntiles, reinterpret_cast<unsigned*>(s_f));

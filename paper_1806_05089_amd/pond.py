@@ -13,7 +13,8 @@ import torch
 
 from . import _lib
 from ._lib import (POND_F32_MIXED, POND_F64, POND_ITERS_BAD, POND_ITERS_MASK,  # noqa: F401
-                   POND_ITERS_NONCONVERGED, POND_PERIODIC, POND_ZERO_GRADIENT, PondError)
+                   POND_ITERS_NONCONVERGED, POND_OP_STEP, POND_OP_STEP_ADJOINT, POND_PERIODIC,
+                   POND_ZERO_GRADIENT, PondError)
 
 
 @dataclasses.dataclass
@@ -105,7 +106,11 @@ def init(cfg: PondConfig, rho, ux, uy, T, device="cuda") -> PondState:
 
 def step(cfg: PondConfig, state_in: PondState, state_out: PondState | None = None,
          nsteps: int = 1, stats: bool = False):
-    """pond_step.  Returns (state_out, stats_dict or None)."""
+    """pond_step.  Returns (state_out, stats_dict or None).
+
+    With nsteps > 1 the library ping-pongs between the two states, so
+    state_in's buffers are overwritten.  stats["iter_hist"][n] counts the
+    nodes that took n predictor-corrector passes in the last step."""
     lib = _lib.load()
     _check_state(cfg, state_in, "state_in")
     if state_out is None:
@@ -117,7 +122,8 @@ def step(cfg: PondConfig, state_in: PondState, state_out: PondState | None = Non
                              _stream_ptr(state_in.f.device), C.byref(st) if stats else None))
     if stats:
         return state_out, {"nonconverged": st.nonconverged, "bad_state": st.bad_state,
-                           "max_iters": st.max_iters, "mean_iters": st.mean_iters}
+                           "max_iters": st.max_iters, "mean_iters": st.mean_iters,
+                           "iter_hist": [int(v) for v in st.iter_hist]}
     return state_out, None
 
 
@@ -134,12 +140,21 @@ def moments(cfg: PondConfig, state: PondState, raw: bool = False):
     return (*outs, M) if raw else tuple(outs)
 
 
+def workspace_bytes(cfg: PondConfig, op: int = POND_OP_STEP_ADJOINT) -> int:
+    """pond_workspace_bytes: caller workspace of an operation."""
+    n = C.c_int64(0)
+    _lib.check(_lib.load().pond_workspace_bytes(C.byref(cfg.c()), int(op), C.byref(n)))
+    return int(n.value)
+
+
 def step_adjoint(cfg: PondConfig, state_in: PondState, state_out: PondState,
-                 adj_f: torch.Tensor, adj_g: torch.Tensor, adj_tau: torch.Tensor | None = None):
+                 adj_f: torch.Tensor, adj_g: torch.Tensor, adj_tau: torch.Tensor | None = None,
+                 workspace: torch.Tensor | None = None):
     """pond_step_adjoint: cotangents at t - dt from cotangents (adj_f, adj_g) at t.
 
     Returns (adj_f_in, adj_g_in); adds d<adj, out>/dtau into adj_tau (a 1-element
-    float64 device tensor) when given.
+    float64 device tensor) when given.  `workspace` is a uint8 device tensor of
+    at least workspace_bytes(cfg) bytes (allocated here when not given).
     """
     lib = _lib.load()
     _check_state(cfg, state_in, "state_in")
@@ -151,14 +166,31 @@ def step_adjoint(cfg: PondConfig, state_in: PondState, state_out: PondState,
     a_in_g = torch.empty_like(adj_g)
     if adj_tau is not None:
         _require(adj_tau, (1,), torch.float64, "adj_tau")
+    if workspace is None:
+        workspace = torch.empty(workspace_bytes(cfg), dtype=torch.uint8, device=dev)
+    if not workspace.is_cuda or workspace.dtype != torch.uint8 or not workspace.is_contiguous():
+        raise ValueError("workspace must be a contiguous uint8 device tensor")
     s_in, s_out = state_in.c(), state_out.c()
     a_out = _lib.pond_state(adj_f.data_ptr(), adj_g.data_ptr(), None)
     a_in = _lib.pond_state(a_in_f.data_ptr(), a_in_g.data_ptr(), None)
     _lib.check(lib.pond_step_adjoint(C.byref(cfg.c()), C.byref(s_in), C.byref(s_out),
                                      C.byref(a_out), C.byref(a_in),
                                      adj_tau.data_ptr() if adj_tau is not None else None,
-                                     _stream_ptr(dev)))
+                                     workspace.data_ptr(), workspace.numel(), _stream_ptr(dev)))
     return a_in_f, a_in_g
+
+
+def init_adjoint(cfg: PondConfig, adj_f: torch.Tensor, adj_g: torch.Tensor):
+    """pond_init_adjoint: (adj_rho, adj_ux, adj_uy, adj_T) from the cotangents
+    of an initial state (f, g) = pond_init(rho, u, T)."""
+    lib = _lib.load()
+    dev = adj_f.device
+    _require(adj_f, (cfg.Q, cfg.ny, cfg.nx), torch.float64, "adj_f")
+    _require(adj_g, (3, cfg.ny, cfg.nx), torch.float64, "adj_g")
+    outs = [torch.empty((cfg.ny, cfg.nx), dtype=torch.float64, device=dev) for _ in range(4)]
+    _lib.check(lib.pond_init_adjoint(C.byref(cfg.c()), adj_f.data_ptr(), adj_g.data_ptr(),
+                                     *[o.data_ptr() for o in outs], _stream_ptr(dev)))
+    return tuple(outs)
 
 
 def tape_bytes(cfg: PondConfig) -> int:

@@ -51,7 +51,8 @@ def test_struct_layout_matches_header():
 int main(void) {
   printf("%zu %zu %zu %zu %zu\n", sizeof(pond_config), offsetof(pond_config, tau),
          offsetof(pond_config, eps_rel), sizeof(pond_state), sizeof(pond_stats));
-  printf("%zu\n", offsetof(pond_stats, mean_iters));
+  printf("%zu %zu\n", offsetof(pond_stats, mean_iters), offsetof(pond_stats, iter_hist));
+  printf("%d %d\n", (int)POND_OP_STEP, (int)POND_OP_STEP_ADJOINT);
   return 0;
 }
 """
@@ -68,10 +69,13 @@ int main(void) {
     assert vals[3] == C.sizeof(_lib.pond_state)
     assert vals[4] == C.sizeof(_lib.pond_stats)
     assert vals[5] == _lib.pond_stats.mean_iters.offset
+    assert vals[6] == _lib.pond_stats.iter_hist.offset
+    assert C.sizeof(_lib.pond_stats) == _lib.pond_stats.iter_hist.offset + 64 * 8
+    assert vals[7:9] == [_lib.POND_OP_STEP, _lib.POND_OP_STEP_ADJOINT]
 
 
 def test_abi_version(lib):
-    assert lib.pond_abi_version() == 101
+    assert lib.pond_abi_version() == 200
 
 
 def _cfg(**kw):
@@ -129,8 +133,9 @@ def test_null_and_alias_checks(lib):
     assert lib.pond_init(C.byref(cfg), None, None, None, None, C.byref(s_out), None) == _lib.POND_E_NULL
     # adjoint needs the forward pass counts
     a_out = _state(f2, g2)
+    ws = (C.c_uint8 * 4096)()
     assert lib.pond_step_adjoint(C.byref(cfg), C.byref(s_in), C.byref(s_in), C.byref(a_out),
-                                 C.byref(a_out), None, None) == _lib.POND_E_NULL
+                                 C.byref(a_out), None, ws, 4096, None) == _lib.POND_E_NULL
     # recorded steps: the tape, and the output's pass counts, are required
     assert lib.pond_tape_bytes(C.byref(cfg), None) == _lib.POND_E_NULL
     tape = (C.c_uint8 * 4096)()
@@ -164,3 +169,85 @@ def test_python_binding_fails_loudly_without_library(tmp_path):
             _lib.load(str(tmp_path / "missing.so"))
         finally:
             _lib._lib = _lib._lib_saved
+
+
+def test_workspace_bytes(lib):
+    """POND_OP_STEP needs none; the adjoint's is the tape plus one state, each
+    part rounded up to 256 bytes."""
+    n = C.c_int64(-1)
+    cfg = _cfg(nx=10, ny=6, max_iter=20)
+    assert lib.pond_workspace_bytes(C.byref(cfg), _lib.POND_OP_STEP, C.byref(n)) == _lib.POND_OK
+    assert n.value == 0
+    assert lib.pond_workspace_bytes(C.byref(cfg), _lib.POND_OP_STEP_ADJOINT,
+                                    C.byref(n)) == _lib.POND_OK
+    up = lambda b: (b + 255) // 256 * 256
+    tape = (21 * 4 + 16) * 60 * 8
+    assert n.value == up(tape) + up(16 * 60 * 8) + up(3 * 60 * 8) + up(60)
+    cfg32 = _cfg(nx=10, ny=6, precision=1, fixed_iter=2)
+    assert lib.pond_workspace_bytes(C.byref(cfg32), _lib.POND_OP_STEP_ADJOINT,
+                                    C.byref(n)) == _lib.POND_OK
+    assert n.value == up((3 * 4 + 16) * 60 * 8) + up(16 * 60 * 4) + up(3 * 60 * 8) + up(60)
+    assert lib.pond_workspace_bytes(C.byref(cfg), 7, C.byref(n)) == _lib.POND_E_INVALID
+    assert lib.pond_workspace_bytes(C.byref(cfg), _lib.POND_OP_STEP, None) == _lib.POND_E_NULL
+
+
+def test_adjoint_workspace_checks(lib):
+    """Missing, too small, misaligned or overlapping workspace: rejected before
+    any launch."""
+    cfg = _cfg(nx=4, ny=4, fixed_iter=2)
+    f1, g1 = (C.c_double * 256)(), (C.c_double * 48)()
+    f2, g2 = (C.c_double * 256)(), (C.c_double * 48)()
+    f3, g3 = (C.c_double * 256)(), (C.c_double * 48)()
+    it = (C.c_uint8 * 16)()
+    s_in, s_fwd = _state(f1, g1), _state(f2, g2, it)
+    a_out, a_in = _state(f2, g2), _state(f3, g3)
+    need = C.c_int64(0)
+    assert lib.pond_workspace_bytes(C.byref(cfg), _lib.POND_OP_STEP_ADJOINT,
+                                    C.byref(need)) == _lib.POND_OK
+    ws = (C.c_uint8 * (need.value + 64))()
+    base = C.addressof(ws)
+    aligned = (base + 15) // 16 * 16
+    call = lambda p, n: lib.pond_step_adjoint(C.byref(cfg), C.byref(s_in), C.byref(s_fwd),
+                                              C.byref(a_out), C.byref(a_in), None, p, n, None)
+    assert call(None, need.value) == _lib.POND_E_NULL
+    assert call(aligned, need.value - 1) == _lib.POND_E_INVALID
+    assert call(aligned + 8, need.value) == _lib.POND_E_INVALID
+    assert "workspace" in lib.pond_last_error().decode()
+    # workspace over the input state
+    big = (C.c_uint8 * (need.value + 4096))()
+    s_in_over = _lib.pond_state((C.addressof(big) + 15) // 16 * 16, C.addressof(g1), None)
+    assert lib.pond_step_adjoint(C.byref(cfg), C.byref(s_in_over), C.byref(s_fwd),
+                                 C.byref(a_out), C.byref(a_in), None,
+                                 (C.addressof(big) + 15) // 16 * 16, need.value,
+                                 None) == _lib.POND_E_ALIAS
+
+
+def test_fp32_mixed_adaptive_rejects_fp64_tolerances(lib):
+    """The paper's FP64 tolerances are below FP32 resolution: an adaptive
+    FP32-mixed step with them is refused (fixed passes need no test)."""
+    f1, g1 = (C.c_float * 256)(), (C.c_double * 48)()
+    f2, g2 = (C.c_float * 256)(), (C.c_double * 48)()
+    s_in, s_out = _state(f1, g1), _state(f2, g2)
+    cfg = _cfg(nx=4, ny=4, precision=1)
+    assert lib.pond_step(C.byref(cfg), C.byref(s_in), C.byref(s_out), 1, None,
+                         None) == _lib.POND_E_INVALID
+    assert "2^-23" in lib.pond_last_error().decode()
+    tape = (C.c_uint8 * 8192)()
+    it = (C.c_uint8 * 16)()
+    s_out_it = _state(f2, g2, it)
+    assert lib.pond_step_record(C.byref(cfg), C.byref(s_in), C.byref(s_out_it), tape,
+                                None) == _lib.POND_E_INVALID
+
+
+def test_init_adjoint_checks(lib):
+    cfg = _cfg(nx=4, ny=4)
+    af, ag = (C.c_double * 256)(), (C.c_double * 48)()
+    assert lib.pond_init_adjoint(C.byref(cfg), None, ag, None, None, None, None,
+                                 None) == _lib.POND_E_NULL
+    # adj_rho inside adj_f
+    assert lib.pond_init_adjoint(C.byref(cfg), af, ag, C.addressof(af) + 64, None, None, None,
+                                 None) == _lib.POND_E_ALIAS
+    bad = _cfg(nx=4, ny=4, q1d=2)
+    out = (C.c_double * 16)()
+    assert lib.pond_init_adjoint(C.byref(bad), af, ag, out, None, None, None,
+                                 None) == _lib.POND_E_INVALID

@@ -220,3 +220,55 @@ def test_recorded_step_and_adjoint(gpu, prec):
     for a, b in ((f2, f1), (g2, g1)):
         assert float(torch.max(torch.abs(a - b))) <= 1e-12 * float(torch.max(torch.abs(b)))
     assert abs(float(t2) - float(t1)) <= 1e-12 * abs(float(t1))
+
+
+def test_adjoint_on_caller_workspace(gpu):
+    """pond_step_adjoint keeps its scratch in the caller's workspace: one
+    filled with garbage and passed at an offset inside a larger buffer gives
+    the adjoint of a freshly allocated one to rounding (the adjoint adds with
+    floating-point atomics); one byte short is refused before any launch."""
+    w = workloads.riemann2d(40, seed=3)
+    cfg = pond.PondConfig(nx=40, ny=40, bc_x=1, bc_y=1, tau=0.55, max_iter=20)
+    st = pond.init(cfg, w.rho, w.ux, w.uy, w.T)
+    st, _ = pond.step(cfg, st, nsteps=3)
+    out, _ = pond.step(cfg, st.clone())
+    gen = torch.Generator(device="cuda").manual_seed(4)
+    wf = torch.randn(out.f.shape, dtype=torch.float64, device="cuda", generator=gen)
+    wg = torch.randn(out.g.shape, dtype=torch.float64, device="cuda", generator=gen)
+    nb = pond.workspace_bytes(cfg)
+    assert nb >= pond.tape_bytes(cfg)
+    big = torch.full((nb + 512,), 0xFF, dtype=torch.uint8, device="cuda")
+    t1 = torch.zeros(1, dtype=torch.float64, device="cuda")
+    t2 = torch.zeros(1, dtype=torch.float64, device="cuda")
+    f1, g1 = pond.step_adjoint(cfg, st, out, wf, wg, t1, workspace=big[256:256 + nb])
+    f2, g2 = pond.step_adjoint(cfg, st, out, wf, wg, t2)
+    for a, b in ((f1, f2), (g1, g2)):
+        assert float(torch.max(torch.abs(a - b))) <= 1e-12 * float(torch.max(torch.abs(b)))
+    assert abs(float(t1) - float(t2)) <= 1e-12 * abs(float(t2))
+    with pytest.raises(pond.PondError):
+        pond.step_adjoint(cfg, st, out, wf, wg, t1, workspace=big[:nb - 1])
+
+
+@pytest.mark.parametrize("q", [4, 3])
+def test_init_adjoint_is_the_transpose_of_init(gpu, q):
+    """pond_init_adjoint against pond_init itself: f = rho W is linear in rho,
+    so <init(rho), a_f> = <rho, adj_rho> for any rho; the gauge cotangents
+    pass through unchanged; adj_rho = sum_p W_p a_f,p with the oracle's
+    weights."""
+    cfg = pond.PondConfig(nx=13, ny=7, q1d=q)
+    rng = np.random.default_rng(q)
+    rho = rng.uniform(0.5, 1.5, (7, 13))
+    zero = np.zeros((7, 13))
+    af = torch.from_numpy(rng.standard_normal((q * q, 7, 13))).cuda()
+    ag = torch.from_numpy(rng.standard_normal((3, 7, 13))).cuda()
+    ar, aux, auy, aT = (t.cpu().numpy() for t in pond.init_adjoint(cfg, af, ag))
+    st = pond.init(cfg, rho, zero, zero, np.ones((7, 13)))
+    lhs = float(torch.sum(st.f * af))
+    assert abs(lhs - float(np.sum(rho * ar))) <= 1e-13 * abs(lhs)
+    agn = ag.cpu().numpy()
+    assert np.array_equal(aux, agn[0]) and np.array_equal(auy, agn[1])
+    assert np.array_equal(aT, agn[2])
+    _, wts, _ = oracle.lattice(q)
+    W = np.outer(wts, wts).reshape(-1)
+    ref = np.tensordot(W, af.cpu().numpy(), axes=1)
+    assert np.max(np.abs(ar - ref)) <= 1e-15 * np.max(np.abs(ref)) * q * q

@@ -118,6 +118,38 @@ def test_adaptive_tail_runs_and_counts(gpu):
     assert abs(stats["mean_iters"] - float(np.mean(ig & pond.POND_ITERS_MASK))) < 1e-12
 
 
+HIST_CASES = [
+    ("smooth_thermal_48x40", lambda: workloads.random_smooth(48, 40, seed=4), 4),
+    ("riemann2d_64", lambda: workloads.riemann2d(64, seed=3), 4),
+    ("d2q9_smooth", lambda: workloads.random_smooth(40, 36, seed=5, T0=1.0 / 3.0, mach=0.2), 3),
+]
+
+
+@pytest.mark.parametrize("name,make,q", HIST_CASES, ids=[c[0] for c in HIST_CASES])
+def test_iteration_histogram(gpu, name, make, q):
+    """pond_stats.iter_hist (App. E's per-node iteration counts as one
+    histogram, reduced on the device) against the step's own pass plane and
+    against the oracle's per-node counts: equal bin for bin where every node
+    took the oracle's count, and off by at most the nodes that did not."""
+    print(f"case {name}", flush=True)
+    w = make()
+    cfg = _cfg(w, q=q, max_iter=20)
+    st = pond.init(cfg, w.rho, w.ux, w.uy, w.T)
+    out, stats = pond.step(cfg, st, stats=True)
+    ig = out.iters.cpu().numpy() & pond.POND_ITERS_MASK
+    hist = np.array(stats["iter_hist"])
+    assert hist.shape == (64,) and hist[0] == 0 and hist.sum() == ig.size
+    assert np.array_equal(hist, np.bincount(ig.ravel(), minlength=64))
+    assert stats["max_iters"] == int(np.max(np.nonzero(hist)[0]))
+    f0, g0 = oracle.init(w.rho, w.ux, w.uy, w.T, q=q)
+    _, _, io, _ = oracle.step(f0, g0, _ocfg(cfg))
+    ho = np.bincount(io.ravel(), minlength=64)
+    ndiff = int(np.sum(io != ig))
+    assert np.sum(np.abs(hist - ho)) <= 2 * ndiff, (hist[:12], ho[:12], ndiff)
+    if ndiff == 0:
+        assert np.array_equal(hist, ho)
+
+
 @pytest.mark.parametrize("nsteps", [1, 2, 5])
 def test_multi_step_pingpong(gpu, nsteps):
     w = workloads.taylor_green(24, mach=0.1)

@@ -38,7 +38,7 @@ def _run(cfg, w, steps):
     return out, stats
 
 
-def test_taylor_green_second_order():
+def test_taylor_green_second_order(gpu):
     errs = []
     for N in (32, 64, 128):
         w = workloads.taylor_green(N, mach=0.01, tau=0.6)
@@ -59,7 +59,7 @@ def test_taylor_green_second_order():
 
 
 @pytest.mark.parametrize("prec", [pond.POND_F64, pond.POND_F32_MIXED])
-def test_sod_full_size_vs_exact(prec):
+def test_sod_full_size_vs_exact(gpu, prec):
     w = workloads.sod(1024, 4)
     cfg = _cfg(w, precision=prec)
     if prec == pond.POND_F32_MIXED:
@@ -80,7 +80,7 @@ def test_sod_full_size_vs_exact(prec):
     assert -0.08 * shock * 400 < sim - xs < 0.0
 
 
-def test_sod_fp32_vs_fp64_error():
+def test_sod_fp32_vs_fp64_error(gpu):
     w = workloads.sod(1024, 4)
     c64 = _cfg(w)
     c32 = _cfg(w, precision=pond.POND_F32_MIXED, eps_abs=1e-6, eps_rel=1e-5)
@@ -95,7 +95,7 @@ def test_sod_fp32_vs_fp64_error():
 
 
 @pytest.mark.parametrize("U,T", [(0.0, 1.0), (5.0, 1.0), (30.0, 0.5), (100.0, 2.0), (300.0, 1.0)])
-def test_uniform_flow_any_mach(U, T):
+def test_uniform_flow_any_mach(gpu, U, T):
     w = workloads.uniform(64, 48, rho=1.3, ux=U, uy=-0.3 * U, T=T)
     cfg = _cfg(w)
     st = pond.init(cfg, w.rho, w.ux, w.uy, w.T)
@@ -105,7 +105,7 @@ def test_uniform_flow_any_mach(U, T):
     assert torch.max(torch.abs(out.g[:2] - st.g[:2])).item() < 1e-13 * max(1.0, U)
 
 
-def test_mach5_galilean_1000_steps_fp32():
+def test_mach5_galilean_1000_steps_fp32(gpu):
     N, steps = 256, 1000
     w0 = workloads.mach5(N, U=0.0, seed=0)
     wU = workloads.mach5(N, U=5.0, seed=0)
@@ -128,7 +128,7 @@ def test_mach5_galilean_1000_steps_fp32():
 
 
 @pytest.mark.parametrize("prec", [pond.POND_F64, pond.POND_F32_MIXED])
-def test_riemann_1024_benchmark_run_stays_physical(prec):
+def test_riemann_1024_benchmark_run_stays_physical(gpu, prec):
     """The benchmark run in full: the 1024^2 four-quadrant Riemann problem for
     2000 adaptive steps ends with no bad node (a bad node's NaN spreads through
     the stencils, so the last step counts every one that ever appeared), with
@@ -146,7 +146,7 @@ def test_riemann_1024_benchmark_run_stays_physical(prec):
     assert torch.isfinite(out.f).all() and torch.isfinite(out.g).all()
 
 
-def test_adjoint_rollout_128_vs_finite_differences():
+def test_adjoint_rollout_128_vs_finite_differences(gpu):
     w = workloads.compressible_taylor_green(128, seed=1)
     nsteps, K = 200, 20
     dev = torch.device("cuda")

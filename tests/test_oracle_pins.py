@@ -476,3 +476,93 @@ def test_complex_step_matches_finite_difference():
     # real part of the complex run is the real run
     fo, go, _, _ = oracle.step(f, g, cfg)
     assert np.max(np.abs(fo_c.real - fo)) < 1e-14 and np.max(np.abs(go_c.real - go)) < 1e-14
+
+
+# ---------------------------------------- the sampled-node entry of the oracle
+STEP_NODES_CASES = [
+    # name, fields, q, bc, fixed passes (0: adaptive)
+    ("d2q16_periodic_fixed", lambda: workloads.random_smooth(23, 17, seed=21, mach=0.7), 4, 0, 3),
+    ("d2q16_periodic_adaptive", lambda: workloads.random_smooth(23, 17, seed=22, mach=0.4), 4, 0, 0),
+    ("d2q16_zero_gradient_adaptive",
+     lambda: workloads.random_smooth(23, 17, seed=23, mach=0.6, dT=0.3), 4, 1, 0),
+    ("d2q16_zero_gradient_fixed", lambda: workloads.random_smooth(23, 17, seed=24), 4, 1, 2),
+    ("d2q9_periodic_fixed",
+     lambda: workloads.random_smooth(23, 17, seed=25, T0=1.0 / 3.0, mach=0.2), 3, 0, 3),
+    ("d2q9_zero_gradient_adaptive",
+     lambda: workloads.random_smooth(23, 17, seed=26, T0=1.0 / 3.0, mach=0.3), 3, 1, 0),
+    # sharp quadrant interfaces: nodes that hit the pass cap
+    ("riemann_23x17_capped", lambda: _riemann_crop(23, 17), 4, 1, 0),
+]
+
+
+def _riemann_crop(nx, ny):
+    w = workloads.riemann2d(32, seed=3)
+    sl = (slice(16 - ny // 2, 16 - ny // 2 + ny), slice(16 - nx // 2, 16 - nx // 2 + nx))
+    return workloads.Workload("riemann_crop", w.rho[sl].copy(), w.ux[sl].copy(), w.uy[sl].copy(),
+                              w.T[sl].copy(), w.tau, 0, 1, 1, 1, {})
+
+
+@pytest.mark.parametrize("name,make,q,bc,fixed", STEP_NODES_CASES,
+                         ids=[c[0] for c in STEP_NODES_CASES])
+def test_step_nodes_equals_step_bitwise(name, make, q, bc, fixed):
+    """oracle.step_nodes, the checker of the full-size sampled parity tests,
+    is oracle.step at the nodes it is given, bit for bit (values, pass counts
+    and status), in any node order."""
+    w = make()
+    f, g = oracle.init(w.rho, w.ux, w.uy, w.T, q=q)
+    cfg = oracle.OracleConfig(q=q, bc_x=bc, bc_y=bc, fixed_iter=fixed, max_iter=8, tau=0.6)
+    # one step first, so that populations leave equilibrium
+    f, g, _, _ = oracle.step(f, g, cfg)
+    fo, go, it, st = oracle.step(f, g, cfg)
+    ny, nx = w.rho.shape
+    nodes = np.random.default_rng(7).permutation(nx * ny)
+    fs, gs, its, sts = oracle.step_nodes(f, g, cfg, nodes)
+    Q = q * q
+    assert np.array_equal(fs, fo.reshape(Q, -1)[:, nodes], equal_nan=True)
+    assert np.array_equal(gs, go.reshape(3, -1)[:, nodes], equal_nan=True)
+    assert np.array_equal(its, it.reshape(-1)[nodes])
+    assert np.array_equal(sts, st.reshape(-1)[nodes])
+    if name.endswith("capped"):
+        assert np.any(st == 1)  # the cap path is exercised
+    if fixed == 0:
+        assert it.max() > it.min()  # adaptive pass counts differ between nodes
+
+
+# ------------------------------------------- the exact Riemann solution itself
+def test_exact_riemann_reproduces_toro_sod_test_1():
+    """Toro, Riemann Solvers and Numerical Methods for Fluid Dynamics (3rd ed.,
+    2009), Table 4.3, test 1 (Sod, gamma = 1.4): p* = 0.30313, u* = 0.92745,
+    rho*_L = 0.42632, rho*_R = 0.26557, to the five digits printed there."""
+    left, right = (1.0, 0.0, 1.0), (0.125, 0.0, 0.1)
+    p_s, u_s = riemann.star_state(left, right, gamma=1.4)
+    assert abs(p_s - 0.30313) < 5e-6 and abs(u_s - 0.92745) < 5e-6
+    r, u, p = riemann.sample(left, right, np.array([u_s - 1e-9, u_s + 1e-9]), gamma=1.4)
+    assert abs(r[0] - 0.42632) < 5e-6 and abs(r[1] - 0.26557) < 5e-6
+    assert np.allclose(u, u_s, atol=0, rtol=0) and np.allclose(p, p_s, atol=0, rtol=0)
+    head, tail, contact, shock = riemann.wave_speeds(left, right, gamma=1.4)
+    assert abs(head + math.sqrt(1.4)) < 1e-15 and contact == u_s
+    # Rankine-Hugoniot across the right shock: mass and momentum fluxes balance
+    rs = r[1]
+    assert abs(rs * (u_s - shock) - 0.125 * (0.0 - shock)) < 1e-12
+    assert abs(rs * (u_s - shock) ** 2 + p_s - (0.125 * shock ** 2 + 0.1)) < 1e-12
+    assert abs(tail - (u_s - math.sqrt(1.4 * p_s / r[0]))) < 1e-12
+
+
+def test_exact_riemann_gamma2_shock_tube_star_state():
+    """The shock tube of the configs with gamma = 2 (2-D monatomic gas,
+    c_s = sqrt(gamma T)): p* = 0.285975, u* = 0.760062, rho*_L = 0.534767,
+    rho*_R = 0.204344, rarefaction head -sqrt(2), tail -0.274120, shock
+    1.957474 (at temperature scale 1; a scale s multiplies speeds by sqrt(s)
+    and leaves densities and p / s unchanged)."""
+    for s in (1.0, 0.25):
+        left, right = (1.0, 0.0, s * 1.0), (0.125, 0.0, s * 0.1)
+        p_s, u_s = riemann.star_state(left, right, gamma=2.0)
+        rs = math.sqrt(s)
+        assert abs(p_s / s - 0.285975) < 5e-7 and abs(u_s / rs - 0.760062) < 5e-7
+        r, _, _ = riemann.sample(left, right, np.array([u_s - 1e-9, u_s + 1e-9]), gamma=2.0)
+        assert abs(r[0] - 0.534767) < 5e-7 and abs(r[1] - 0.204344) < 5e-7
+        head, tail, contact, shock = riemann.wave_speeds(left, right, gamma=2.0)
+        assert abs(head / rs + math.sqrt(2.0)) < 1e-12
+        assert abs(tail / rs + 0.274120) < 5e-7 and abs(shock / rs - 1.957474) < 5e-7
+        # isentropic left fan: p / rho^gamma constant into the star region
+        assert abs(p_s / r[0] ** 2 - s * 1.0) < 1e-12 * s
