@@ -220,13 +220,31 @@ int pond_step_adjoint_recorded(const pond_config* cfg, const pond_state* in,
                                const pond_state* adj_out, pond_state* adj_in, double* adj_tau,
                                void* hip_stream);
 
+/*
+ * pond_step for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments, arithmetic and results as pond_step (bit for bit); it calls no
+ * hipMalloc / hipFree and allocates nothing through any library.  Its step
+ * counters, tile queue and tile cost/order arrays live in one fixed device
+ * array of the library (about 386 KiB per GPU, held until the process ends),
+ * sized for at most 65,536 step tiles (tiles of 32 x 16 nodes in POND_F64,
+ * 32 x 8 in POND_F32_MIXED: any grid up to 4096 x 4096); a larger grid is
+ * rejected with POND_E_INVALID.  The queue is cleared by a fill kernel at
+ * every call (no memset).  Every call on one GPU shares that GPU's array:
+ * calls that overlap on one GPU (different streams, or threads) race and are
+ * not supported; calls in order on one stream are.
+ */
+int pond_step_noalloc(const pond_config* cfg, pond_state* in, pond_state* out, int32_t nsteps,
+                      void* hip_stream, pond_stats* stats);
+
 /* Message for the last nonzero return on this thread ("" if none). */
 const char* pond_last_error(void);
 
 /* ABI version of this header (major * 100 + minor).  101 added the recorded
  * steps (pond_tape_bytes, pond_step_record, pond_step_adjoint_recorded); 200:
  * the pass histogram in pond_stats, pond_step_adjoint on caller workspace
- * (pond_workspace_bytes), pond_init_adjoint, `in` of pond_step not const. */
+ * (pond_workspace_bytes), pond_init_adjoint, `in` of pond_step not const;
+ * 201 adds pond_step_noalloc. */
 int pond_abi_version(void);
 
 #ifdef __cplusplus

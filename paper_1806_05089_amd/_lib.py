@@ -28,7 +28,8 @@ POND_ITERS_BAD = 0x80
 
 EXPORTED = ("pond_init", "pond_step", "pond_moments", "pond_step_adjoint", "pond_last_error",
             "pond_abi_version", "pond_tape_bytes", "pond_step_record",
-            "pond_step_adjoint_recorded", "pond_workspace_bytes", "pond_init_adjoint")
+            "pond_step_adjoint_recorded", "pond_workspace_bytes", "pond_init_adjoint",
+            "pond_step_noalloc")
 
 
 class pond_config(C.Structure):
@@ -90,6 +91,8 @@ def load(path: str | None = None):
     lib.pond_workspace_bytes.restype = C.c_int
     lib.pond_init_adjoint.argtypes = [cp, dp, dp, dp, dp, dp, dp, dp]
     lib.pond_init_adjoint.restype = C.c_int
+    lib.pond_step_noalloc.argtypes = [cp, sp, sp, C.c_int32, dp, C.POINTER(pond_stats)]
+    lib.pond_step_noalloc.restype = C.c_int
     lib.pond_last_error.argtypes = []
     lib.pond_last_error.restype = C.c_char_p
     lib.pond_abi_version.argtypes = []

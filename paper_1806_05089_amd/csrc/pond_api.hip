@@ -277,13 +277,53 @@ int launch_adjoint_on(const pond_config& c, Slot* slot, const pond_state* in,
   return POND_OK;
 }
 
+// ---- scratch of pond_step_noalloc: one fixed device array per GPU ----
+// Layout: step counters at 0, the tile queue at 1 KiB, the tile cost keys at
+// 2 KiB (uint16 per tile), the tile order after them (uint32 per tile).
+constexpr size_t kNoAllocTiles = 65536;  // 4096^2 in both precisions
+constexpr size_t kScratchQueue = 1024;
+constexpr size_t kScratchKeys = 2048;
+constexpr size_t kScratchOrder = kScratchKeys + kNoAllocTiles * sizeof(uint16_t);
+constexpr size_t kScratchBytes = kScratchOrder + kNoAllocTiles * sizeof(unsigned);
+static_assert(sizeof(pond::StepCounters) <= kScratchQueue, "counters fit their part");
+static_assert(sizeof(pond::TileQueue) <= kScratchKeys - kScratchQueue, "queue fits its part");
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+// Per device: the scratch array's device address (from hipGetSymbolAddress;
+// the array's name is a host-side stand-in, never a device address) and the
+// grid whose tile order the array holds.
+struct NoAllocDevice {
+  char* ptr = nullptr;
+  int order_nx = -1, order_ny = -1;
+  unsigned order_tiles = 0;
+};
+std::mutex g_noalloc_mutex;
+std::map<int, NoAllocDevice> g_noalloc;
+
+int noalloc_scratch(NoAllocDevice** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  std::lock_guard<std::mutex> lock(g_noalloc_mutex);
+  NoAllocDevice& d = g_noalloc[dev];
+  if (!d.ptr) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    d.ptr = static_cast<char*>(p);
+  }
+  *out = &d;
+  return POND_OK;
+}
+
 }  // namespace
 
 extern "C" {
 
 const char* pond_last_error(void) { return g_last_error.c_str(); }
 
-int pond_abi_version(void) { return 200; }
+int pond_abi_version(void) { return 201; }
 
 int pond_init(const pond_config* cfg, const double* rho, const double* ux, const double* uy,
               const double* T, pond_state* out, void* hip_stream) {
@@ -514,6 +554,108 @@ int pond_init_adjoint(const pond_config* cfg, const double* adj_f, const double*
   const hipError_t e = pond::launch_init_adjoint(*cfg, adj_f, adj_g, adj_rho, adj_ux, adj_uy,
                                                  adj_T, static_cast<hipStream_t>(hip_stream));
   if (e != hipSuccess) return hip_fail(e, "pond_init_adjoint launch");
+  return POND_OK;
+}
+
+int pond_step_noalloc(const pond_config* cfg, pond_state* in, pond_state* out, int32_t nsteps,
+                      void* hip_stream, pond_stats* stats) {
+  g_last_error.clear();
+  int rc = check_config(cfg);
+  if (rc) return rc;
+  if ((rc = check_step_tolerances(cfg, "pond_step_noalloc"))) return rc;
+  if (!in || !out || !in->f || !in->g || !out->f || !out->g)
+    return fail(POND_E_NULL, "pond_step_noalloc: a state buffer is NULL");
+  if (nsteps < 1) return fail(POND_E_INVALID, "pond_step_noalloc: nsteps must be >= 1");
+  const unsigned ntiles = pond::step_tile_count(*cfg);
+  if (ntiles > kNoAllocTiles) {
+    char buf[160];
+    snprintf(buf, sizeof(buf),
+             "pond_step_noalloc: %u step tiles exceed the fixed scratch (%zu tiles: 4096 x 4096 "
+             "nodes); use pond_step", ntiles, kNoAllocTiles);
+    return fail(POND_E_INVALID, buf);
+  }
+  const size_t fb = f_bytes(*cfg), gb = g_bytes(*cfg);
+  if (overlap(in->f, fb, out->f, fb) || overlap(in->g, gb, out->g, gb) ||
+      overlap(in->f, fb, out->g, gb) || overlap(in->g, gb, out->f, fb))
+    return fail(POND_E_ALIAS, "pond_step_noalloc: input and output state overlap");
+  NoAllocDevice* d = nullptr;
+  if ((rc = noalloc_scratch(&d))) return rc;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  pond::StepCounters* cnt = reinterpret_cast<pond::StepCounters*>(d->ptr);
+  pond::TileQueue* queue = reinterpret_cast<pond::TileQueue*>(d->ptr + kScratchQueue);
+  // The array keeps the last call's contents: the queue must start empty.
+  hipError_t e = pond::launch_zero_u64(reinterpret_cast<unsigned long long*>(queue), 1, s);
+  if (e != hipSuccess) return hip_fail(e, "pond_step_noalloc zero queue");
+
+  pond::StepArgs a;
+  a.nx = cfg->nx;
+  a.ny = cfg->ny;
+  a.bc_x = cfg->bc_x;
+  a.bc_y = cfg->bc_y;
+  a.max_iter = cfg->max_iter;
+  a.fixed_iter = cfg->fixed_iter;
+  a.seed_mode = cfg->seed_mode;
+  a.isothermal = cfg->isothermal;
+  a.bulk_cap = bulk_cap(cfg->precision);
+  a.tau = cfg->tau;
+  a.eps_abs = cfg->eps_abs;
+  a.eps_rel = cfg->eps_rel;
+  a.iters = out->iters;
+  a.queue = queue;
+  a.tile_keys = reinterpret_cast<uint16_t*>(d->ptr + kScratchKeys);
+  a.tile_order_next = reinterpret_cast<unsigned*>(d->ptr + kScratchOrder);
+  a.tile_cap = (unsigned)kNoAllocTiles;
+  a.tape = nullptr;
+  a.tape_f = nullptr;
+
+  const void* src_f = in->f;
+  const double* src_g = in->g;
+  for (int k = 0; k < nsteps; ++k) {
+    const bool to_out = (k % 2 == 0);
+    void* dst_f = to_out ? out->f : in->f;
+    double* dst_g = to_out ? out->g : in->g;
+    a.f_in = src_f;
+    a.g_in = src_g;
+    a.f_out = dst_f;
+    a.g_out = dst_g;
+    a.counters = (k == nsteps - 1 && stats) ? cnt : nullptr;
+    if (a.counters) {
+      e = pond::launch_zero_u64(reinterpret_cast<unsigned long long*>(cnt),
+                                pond::kStepCounterWords, s);
+      if (e != hipSuccess) return hip_fail(e, "pond_step_noalloc zero counters");
+    }
+    {
+      // the order left in the array is a permutation of this grid's tiles
+      // only if the last call on this device had the same grid and tile count
+      std::lock_guard<std::mutex> lock(g_noalloc_mutex);
+      const bool ordered = d->order_nx == cfg->nx && d->order_ny == cfg->ny &&
+                           d->order_tiles == ntiles;
+      a.tile_order = ordered ? a.tile_order_next : nullptr;
+      e = pond::launch_step(*cfg, a, s);
+      d->order_nx = e == hipSuccess ? cfg->nx : -1;
+      d->order_ny = e == hipSuccess ? cfg->ny : -1;
+      d->order_tiles = ntiles;
+    }
+    if (e != hipSuccess) return hip_fail(e, "pond_step_noalloc launch");
+    src_f = dst_f;
+    src_g = dst_g;
+  }
+  if (nsteps % 2 == 0) {
+    e = hipMemcpyAsync(out->f, in->f, fb, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(out->g, in->g, gb, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "pond_step_noalloc final copy");
+  }
+  if (stats) {
+    pond::StepCounters h;
+    e = hipMemcpyAsync(&h, cnt, sizeof(h), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "pond_step_noalloc stats");
+    stats->nonconverged = (int64_t)h.nonconverged;
+    stats->bad_state = (int64_t)h.bad;
+    stats->max_iters = (int32_t)h.max_passes;
+    stats->mean_iters = (double)h.sum_passes / ((double)cfg->nx * cfg->ny);
+    for (int k = 0; k <= POND_ITERS_MASK; ++k) stats->iter_hist[k] = (int64_t)h.hist[k];
+  }
   return POND_OK;
 }
 

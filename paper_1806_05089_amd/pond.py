@@ -127,6 +127,26 @@ def step(cfg: PondConfig, state_in: PondState, state_out: PondState | None = Non
     return state_out, None
 
 
+def step_noalloc(cfg: PondConfig, state_in: PondState, state_out: PondState,
+                 nsteps: int = 1, stats: bool = False):
+    """pond_step_noalloc: pond_step on the library's fixed scratch (no device
+    allocation by the library; both states are the caller's).  Returns
+    (state_out, stats_dict or None)."""
+    lib = _lib.load()
+    _check_state(cfg, state_in, "state_in")
+    _check_state(cfg, state_out, "state_out")
+    cin, cout = state_in.c(), state_out.c()
+    st = _lib.pond_stats() if stats else None
+    _lib.check(lib.pond_step_noalloc(C.byref(cfg.c()), C.byref(cin), C.byref(cout), int(nsteps),
+                                     _stream_ptr(state_in.f.device),
+                                     C.byref(st) if stats else None))
+    if stats:
+        return state_out, {"nonconverged": st.nonconverged, "bad_state": st.bad_state,
+                           "max_iters": st.max_iters, "mean_iters": st.mean_iters,
+                           "iter_hist": [int(v) for v in st.iter_hist]}
+    return state_out, None
+
+
 def moments(cfg: PondConfig, state: PondState, raw: bool = False):
     """pond_moments.  Returns (rho, ux, uy, T[, Mmn]) as float64 device tensors."""
     lib = _lib.load()

@@ -75,7 +75,7 @@ int main(void) {
 
 
 def test_abi_version(lib):
-    assert lib.pond_abi_version() == 200
+    assert lib.pond_abi_version() == 201
 
 
 def _cfg(**kw):
@@ -251,3 +251,24 @@ def test_init_adjoint_checks(lib):
     out = (C.c_double * 16)()
     assert lib.pond_init_adjoint(C.byref(bad), af, ag, out, None, None, None,
                                  None) == _lib.POND_E_INVALID
+
+
+def test_step_noalloc_argument_checks(lib):
+    """pond_step_noalloc checks like pond_step, and refuses a grid whose step
+    tiles exceed its fixed scratch, before any HIP call."""
+    f1, g1 = (C.c_double * 256)(), (C.c_double * 48)()
+    f2, g2 = (C.c_double * 256)(), (C.c_double * 48)()
+    s_in, s_out = _state(f1, g1), _state(f2, g2)
+    cfg = _cfg(nx=4, ny=4)
+    assert lib.pond_step_noalloc(C.byref(cfg), C.byref(s_in), None, 1, None,
+                                 None) == _lib.POND_E_NULL
+    s_alias = _state(f1, g2)
+    assert lib.pond_step_noalloc(C.byref(cfg), C.byref(s_in), C.byref(s_alias), 1, None,
+                                 None) == _lib.POND_E_ALIAS
+    assert lib.pond_step_noalloc(C.byref(cfg), C.byref(s_in), C.byref(s_out), 0, None,
+                                 None) == _lib.POND_E_INVALID
+    # 4096 x 4100 in FP32-mixed: 128 x 513 tiles of 32 x 8 > 65,536
+    big = _cfg(nx=4096, ny=4100, precision=1, eps_abs=1e-6, eps_rel=1e-5)
+    assert lib.pond_step_noalloc(C.byref(big), C.byref(s_in), C.byref(s_out), 1, None,
+                                 None) == _lib.POND_E_INVALID
+    assert "scratch" in lib.pond_last_error().decode()
