@@ -287,14 +287,38 @@ __device__ __forceinline__ void transfer_factor_deriv(double r, double d, double
 }
 
 
-// Error-free sum (Knuth TwoSum) for compensated accumulation.
+// Error-free sum (Knuth TwoSum) for compensated accumulation.  Contraction
+// is off here: the error term is exact only if t is the rounded sum of s and
+// x as written.
 template <class R>
 __device__ __forceinline__ void two_sum_acc(R& s, R& c, R x) {
+#pragma clang fp contract(off)
   const R t = s + x;
   const R bp = t - s;
   c += (s - (t - bp)) + (x - bp);
   s = t;
 }
+
+// One term of a compensated dot product (Ogita, Rump & Oishi 2005, Dot2)
+// with a constant factor a = a_hi + a_lo held as two values of type R: the
+// product a_hi x is split exactly by one FMA (TwoProduct), its sum with s by
+// TwoSum, and both rounding errors plus a_lo x go into the compensation c.
+// The result carries the accuracy of a sum in twice the working precision.
+template <class R>
+__device__ __forceinline__ void dot2_acc(R& s, R& c, R a_hi, R a_lo, R x) {
+#pragma clang fp contract(off)
+  const R p = a_hi * x;
+  const R pe = fma(a_hi, x, -p);
+  const R t = s + p;
+  const R bp = t - s;
+  c += ((s - (t - bp)) + (p - bp)) + fma(a_lo, x, pe);
+  s = t;
+}
+
+// A double constant split into the nearest FP32 value and the FP32 rounding
+// of the remainder (hi + lo equals it to about 2^-48 relative).
+__host__ __device__ constexpr float split_hi(double a) { return float(a); }
+__host__ __device__ constexpr float split_lo(double a) { return float(a - double(float(a))); }
 
 // LDS layout of the staged window: the Q values of a window node are kept in
 // groups of G = 16 / sizeof(FT) populations whose values are adjacent, so

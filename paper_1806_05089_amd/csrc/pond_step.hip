@@ -412,20 +412,36 @@ __device__ __forceinline__ void tail_group(const StepArgs& A, const FT* s_f, int
       }
       fij = pop ? acc : FT(0);
     }
-    // a6 over the 16 lanes of the group (compensated pairwise sums)
+    // a6 over the 16 lanes of the group (compensated pairwise sums; in
+    // FP32 the products with the speeds are split exactly as in the one-lane
+    // form, and the speeds are held as FP32 pairs)
     const bool live = !gdone && pop;
-    FT v[4] = {live ? fij : FT(0), live ? FT(ci) * fij : FT(0), live ? FT(cj) * fij : FT(0),
-               live ? FT(ci * ci + cj * cj) * fij : FT(0)};
-    FT er[4] = {FT(0), FT(0), FT(0), FT(0)};
+    FT v[4], er[4];
+    {
+#pragma clang fp contract(off)
+      v[0] = live ? fij : FT(0);
+      v[1] = live ? FT(ci) * fij : FT(0);
+      v[2] = live ? FT(cj) * fij : FT(0);
+      v[3] = live ? FT(ci * ci + cj * cj) * fij : FT(0);
+      er[0] = er[1] = er[2] = er[3] = FT(0);
+      if constexpr (sizeof(FT) == 4) {
+        const double cv[3] = {ci, cj, ci * ci + cj * cj};
 #pragma unroll
-    for (int off = 8; off > 0; off >>= 1) {
+        for (int k = 1; k < 4; ++k) {
+          const float hi = split_hi(cv[k - 1]), lo = split_lo(cv[k - 1]);
+          er[k] = live ? fmaf(hi, fij, -v[k]) + lo * fij : 0.0f;
+        }
+      }
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const FT ov = __shfl_xor(v[k], off), oe = __shfl_xor(er[k], off);
-        const FT t = v[k] + ov;
-        const FT bp = t - v[k];
-        er[k] += oe + ((v[k] - (t - bp)) + (ov - bp));
-        v[k] = t;
+      for (int off = 8; off > 0; off >>= 1) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const FT ov = __shfl_xor(v[k], off), oe = __shfl_xor(er[k], off);
+          const FT t = v[k] + ov;
+          const FT bp = t - v[k];
+          er[k] += oe + ((v[k] - (t - bp)) + (ov - bp));
+          v[k] = t;
+        }
       }
     }
     if (!gdone) {
@@ -986,8 +1002,9 @@ k_step(StepArgs A) {
 
         // a6: moments in the peculiar frame of lambda_n.  FP64: plain fused
         // sums (rounding ~1e-16 of the moments, far below the App. E
-        // tolerances).  FP32-mixed: FP32 accumulation with TwoSum
-        // compensation.
+        // tolerances).  FP32-mixed: FP32 accumulation compensated as a
+        // Dot2 dot product: the products with the speeds split exactly,
+        // the speeds held as FP32 pairs, the sums by TwoSum.
         double r0, mx, my, e2;
         if constexpr (sizeof(FT) == 8) {
           r0 = mx = my = e2 = 0.0;
@@ -1002,17 +1019,41 @@ k_step(StepArgs A) {
               e2 = fma(L::c(i) * L::c(i) + L::c(j) * L::c(j), fv, e2);
             }
         } else {
-          FT a0 = 0, a0c = 0, ax = 0, axc = 0, ay = 0, ayc = 0, ae = 0, aec = 0;
+          // Row sums S_i = sum_j f_ij and column sums C_j = sum_i f_ij, each
+          // with its TwoSum error; then rho = sum S_i and the speed-weighted
+          // moments sum_i c_i S_i, sum_j c_j C_j, sum_i c_i^2 S_i +
+          // sum_j c_j^2 C_j as Dot2 sums (a sum's error term enters with
+          // the plain product): Q1 products per moment instead of Q.
+          FT S[Q1], Se[Q1], C[Q1], Ce[Q1];
+#pragma unroll
+          for (int k = 0; k < Q1; ++k) {
+            S[k] = ft[k * Q1];
+            C[k] = ft[k];
+            Se[k] = Ce[k] = FT(0);
+          }
 #pragma unroll
           for (int i = 0; i < Q1; ++i)
 #pragma unroll
             for (int j = 0; j < Q1; ++j) {
-              const FT fv = ft[i * Q1 + j];
-              two_sum_acc(a0, a0c, fv);
-              two_sum_acc(ax, axc, FT(L::c(i)) * fv);
-              two_sum_acc(ay, ayc, FT(L::c(j)) * fv);
-              two_sum_acc(ae, aec, FT(L::c(i) * L::c(i) + L::c(j) * L::c(j)) * fv);
+              if (j > 0) two_sum_acc(S[i], Se[i], ft[i * Q1 + j]);
+              if (i > 0) two_sum_acc(C[j], Ce[j], ft[i * Q1 + j]);
             }
+          FT a0 = S[0], a0c = Se[0], ax = 0, axc = 0, ay = 0, ayc = 0, ae = 0, aec = 0;
+#pragma unroll
+          for (int k = 0; k < Q1; ++k) {
+            const double ck = L::c(k), ck2 = ck * ck;
+            if (k > 0) {
+              two_sum_acc(a0, a0c, S[k]);
+              a0c += Se[k];
+            }
+            dot2_acc(ax, axc, split_hi(ck), split_lo(ck), S[k]);
+            axc = fma(FT(ck), Se[k], axc);
+            dot2_acc(ay, ayc, split_hi(ck), split_lo(ck), C[k]);
+            ayc = fma(FT(ck), Ce[k], ayc);
+            dot2_acc(ae, aec, split_hi(ck2), split_lo(ck2), S[k]);
+            dot2_acc(ae, aec, split_hi(ck2), split_lo(ck2), C[k]);
+            aec = fma(FT(ck2), Se[k] + Ce[k], aec);
+          }
           r0 = double(a0) + double(a0c);
           mx = double(ax) + double(axc);
           my = double(ay) + double(ayc);
