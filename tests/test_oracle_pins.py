@@ -456,6 +456,123 @@ def test_sod_vs_exact_riemann():
     assert -0.08 * shock * steps < sim_shock - xs < 0.0
 
 
+def test_pass_with_uniform_departure_offsets_conserves_mass():
+    """Where every node's departure offsets are equal (a uniform gauge), the
+    cubic weights of App. C taken over all targets of one source sum to one,
+    and the transfer of eq. (4) keeps the density: one pass then conserves
+    the total mass to rounding, whatever the density field.  A second pass
+    runs with the corrector gauges of the first, which differ from node to
+    node, and the total mass moves: the semi-Lagrangian step of eq. (5) is
+    conservative only up to the variation of the departure offsets."""
+    w = workloads.random_smooth(16, 12, seed=31, mach=0.0)
+    rng = np.random.default_rng(31)
+    rho = 1.0 + 0.2 * rng.standard_normal(w.rho.shape)
+    ux, uy, T = (np.full(rho.shape, v) for v in (0.37, -0.21, 0.8))
+    f, g = oracle.init(rho, ux, uy, T)
+    m0 = f.sum()
+    f1, g1, _, _ = oracle.step(f, g, oracle.OracleConfig(fixed_iter=1, tau=0.6))
+    assert abs(f1.sum() - m0) / m0 < 1e-13
+    f2, g2, _, _ = oracle.step(f, g, oracle.OracleConfig(fixed_iter=2, tau=0.6))
+    assert abs(f2.sum() - m0) / m0 > 1e-9
+
+
+def _sod_defects(nx, steps, tau):
+    w = workloads.sod(nx, 1, tau=tau)
+    f, g = oracle.init(w.rho, w.ux, w.uy, w.T)
+    cfg = oracle.OracleConfig(bc_x=1, tau=tau)
+
+    def totals(f, g):
+        rho, ux, _, T = oracle.moments(f, g)
+        return np.array([rho.sum(), (rho * ux).sum(), (0.5 * rho * ux ** 2 + rho * T).sum()])
+
+    t0 = totals(f, g)
+    for _ in range(steps):
+        f, g, _, st = oracle.step(f, g, cfg)
+        assert not np.any(st == 2)
+    t1 = totals(f, g)
+    # before the waves reach the ends: mass and energy are constant and the
+    # momentum grows by (p_L - p_R) per step, p = scale * (1, 0.1)
+    dp_exact = w.meta["scale"] * 0.9 * steps
+    return (t1[0] - t0[0]) / t0[0], (t1[1] - t0[1] - dp_exact) / dp_exact, (t1[2] - t0[2]) / t0[2]
+
+
+def test_sod_nonconservation_is_set_by_the_jumps():
+    """Known deviation of the shock tube (the shock ~5 % slow): over the same
+    time in units of the tube length, the relative defects of mass, momentum
+    and energy are the same at two resolutions with the same tau, so they
+    come from the discontinuities, whose width in nodes does not change with
+    the grid, and not from a truncation error that shrinks with it.  Mass is
+    gained and energy lost; the momentum grows about 1 % slower than the
+    pressure difference drives it."""
+    d1 = _sod_defects(128, 50, 0.52)
+    d2 = _sod_defects(256, 100, 0.52)
+    for dm, dp, de in (d1, d2):
+        assert 2e-4 < dm < 1e-3
+        assert -2e-2 < dp < -5e-3
+        assert -3e-2 < de < -1e-2
+    assert 0.8 < d2[0] / d1[0] < 1.25 and 0.7 < d2[2] / d1[2] < 1.0
+
+
+def _pc_map_at(w, X):
+    """lambda -> gauge after one pass at node X, all other nodes unchanged
+    (node X's populations re-expressed in lambda by eq. (4), which leaves
+    them the same source for every target)."""
+    f, g = oracle.init(w.rho, w.ux, w.uy, w.T)
+    cfg = oracle.OracleConfig(bc_x=1, tau=w.tau, fixed_iter=1)
+    src = tuple(g[:, 0, X])
+
+    def F(lam):
+        u, T = lam
+        if not (np.isfinite(u) and np.isfinite(T)) or T <= 0.0:
+            return np.array([10.0, 10.0])
+        f2, g2 = f.copy(), g.copy()
+        f2[:, 0, X] = oracle.transfer_2d(4, src, (u, 0.0, T)) @ f[:, 0, X]
+        g2[:, 0, X] = (u, 0.0, T)
+        _, go, _, st = oracle.step(f2, g2, cfg)
+        if st[0, X] == 2:
+            return np.array([10.0, 10.0])
+        return np.array([go[0, 0, X] - u, go[2, 0, X] - T])
+
+    return F, (src[0], src[2])
+
+
+def test_sharp_diaphragm_corrector_has_no_fixed_point():
+    """At a one-node jump of the shock tube, the first node downstream has no
+    self-consistent gauge: the predictor-corrector map of eqs. (5), (10)-(12)
+    has no fixed point near the flow's states, and from the stored gauge the
+    iterates lose temperature on every pass until it goes negative.  This is
+    the method at a discontinuity, not the seed (the map itself lacks the
+    fixed point) and not the finite-n regauge (nothing is regauged before the
+    test passes).  With the diaphragm spread by tanh over one node the fixed
+    point exists, is found from any start, and the iteration converges to it."""
+    from scipy.optimize import least_squares
+    X = 32
+    Fs, seed = _pc_map_at(workloads.sod(64, 1, width=0.0), X)
+    best = min((least_squares(Fs, s0, bounds=([-0.5, 0.01], [1.5, 1.0])) for s0 in
+                [(0.43, 0.19), (0.2, 0.3), (0.6, 0.25)]), key=lambda r: r.cost)
+    assert np.max(np.abs(best.fun)) > 5e-3
+    lam, Ts = np.array(seed), []
+    for _ in range(8):
+        lam = lam + Fs(lam)
+        Ts.append(lam[1])
+    assert np.all(np.diff(Ts) < 0)
+    f, g = oracle.init(*(getattr(workloads.sod(64, 1, width=0.0), k) for k in ("rho", "ux", "uy", "T")))
+    _, _, _, st = oracle.step(f, g, oracle.OracleConfig(bc_x=1, tau=0.52))
+    assert st[0, X] == 2
+
+    w1 = workloads.sod(64, 1, width=1.0)
+    F1, _ = _pc_map_at(w1, X)
+    roots = [least_squares(F1, s0, bounds=([-0.5, 0.01], [1.5, 1.0])) for s0 in
+             [(0.43, 0.19), (0.2, 0.3), (0.6, 0.25)]]
+    for r in roots:
+        assert np.max(np.abs(r.fun)) < 1e-9
+        assert np.allclose(r.x, roots[0].x, atol=1e-6)
+    f, g = oracle.init(w1.rho, w1.ux, w1.uy, w1.T)
+    _, go, _, st = oracle.step(f, g, oracle.OracleConfig(bc_x=1, tau=w1.tau))
+    assert st[0, X] == 0
+    assert abs(go[0, 0, X] - roots[0].x[0]) < 1e-6 and abs(go[2, 0, X] - roots[0].x[1]) < 1e-6
+
+
 # --------------------------------------------- complex-step consistency
 def test_complex_step_matches_finite_difference():
     w = workloads.random_smooth(8, 7, seed=9, mach=0.3)
