@@ -22,10 +22,11 @@ def _load():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(_LIB_PATH):
+    path = os.environ.get("POND_ORACLE_LIBRARY", _LIB_PATH)  # another build of the same source
+    if path == _LIB_PATH and not os.path.exists(_LIB_PATH):
         from .build_oracle import build
         build()
-    lib = C.CDLL(_LIB_PATH)
+    lib = C.CDLL(path)
     I, D = C.c_int, C.c_double
     lib.oracle_lattice.argtypes = [I, _dp, _dp, _dp]
     lib.oracle_transfer_1d.argtypes = [I, D, D, D, D, _dp]

@@ -12,14 +12,14 @@ SRC = os.path.join(HERE, "pond_oracle.cpp")
 LIB = os.path.join(HERE, "libpond_oracle.so")
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, extra_flags=(), out: str = LIB) -> str:
     cmd = ["g++", "-std=c++17", "-O2", "-fopenmp", "-fPIC", "-shared", "-fno-fast-math",
-           "-ffp-contract=off", "-o", LIB + ".tmp", SRC]
+           "-ffp-contract=off", *extra_flags, "-o", out + ".tmp", SRC]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(LIB + ".tmp", LIB)
-    return LIB
+    os.replace(out + ".tmp", out)
+    return out
 
 
 if __name__ == "__main__":

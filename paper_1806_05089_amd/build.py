@@ -25,18 +25,29 @@ HIPCC_FLAGS = [
 ]
 
 
-def build(verbose: bool = False, extra_flags=()) -> str:
+# Checking build: the same library with every LDS window filled with NaN
+# before it is staged (a kernel that read a window value it had not staged
+# would return NaN there); the tests compare it with libpond.so.
+POISON_LIB = os.path.join(PKG, "libpond_ldspoison.so")
+
+
+def build(verbose: bool = False, extra_flags=(), out: str = LIB) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    tmp = LIB + ".tmp"
+    tmp = out + ".tmp"
     cmd = [hipcc, *HIPCC_FLAGS, *extra_flags, "-I", INCLUDE, "-I", CSRC, "-o", tmp, *srcs]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
+
+
+def build_poison(verbose: bool = False) -> str:
+    return build(verbose, ("-DPOND_LDS_POISON",), POISON_LIB)
 
 
 if __name__ == "__main__":
     build(verbose=True)
+    build_poison(verbose=True)
     sys.exit(0)

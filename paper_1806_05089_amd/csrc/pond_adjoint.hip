@@ -665,6 +665,12 @@ k_step_adjoint(AdjArgs A) {
     }
     const double inv_sB = 1.0 / sB;
 
+#ifdef POND_LDS_POISON
+    // checking build: every staged value that the loop below does not write
+    // reads as NaN, so a read of an unstaged value shows in the output
+    for (int k = tid; k < Win<Q1, double, WN>::size; k += NT) s_fB[k] = __builtin_nan("");
+    __syncthreads();
+#endif
     // stage f^B = G_{s->B} f_s and clear the accumulators
     for (int k = tid; k < WN; k += NT) {
       const int wy = k / WX, wx = k - wy * WX;

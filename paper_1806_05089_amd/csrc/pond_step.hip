@@ -662,6 +662,12 @@ k_step(StepArgs A) {
       wy0 = nyn <= WY ? ylo - (WY - nyn) / 2 : (int)(((long long)ylo + yhi) / 2) - WY / 2;
     }
 
+#ifdef POND_LDS_POISON
+    // checking build: every window value that the staging below does not
+    // write reads as NaN, so a read of an unstaged value shows in the output
+    for (int k = tid; k < Win<Q1, FT, WN>::size; k += NT) s_f[k] = FT(__builtin_nan(""));
+    __syncthreads();
+#endif
     // ---- stage the window in the reference gauge (eq. 4, G_{s->B}) ----
     {
       const double inv_sB = 1.0 / sB;

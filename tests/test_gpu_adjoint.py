@@ -272,3 +272,34 @@ def test_init_adjoint_is_the_transpose_of_init(gpu, q):
     W = np.outer(wts, wts).reshape(-1)
     ref = np.tensordot(W, af.cpu().numpy(), axes=1)
     assert np.max(np.abs(ar - ref)) <= 1e-15 * np.max(np.abs(ref)) * q * q
+
+
+def test_adjoint_scatter_order_only_moves_rounding(gpu, monkeypatch):
+    """The adjoint adds collocation cotangents with floating-point atomics, so
+    its result depends on the order in which tiles and lanes add.  Repeated
+    calls, and the one-, two- and four-lane kernels (different tiles, a node's
+    y speeds split over lanes), must agree to the rounding of those sums:
+    1e-13 of the largest entry.  Every element is checked against the
+    oracle's complex step by test_vjp_elementwise_tiny_grid; the dot products
+    above check multi-tile grids."""
+    w = workloads.riemann2d(56, seed=3)
+    cfg = pond.PondConfig(nx=56, ny=56, bc_x=1, bc_y=1, tau=0.55, fixed_iter=3)
+    st = pond.init(cfg, w.rho, w.ux, w.uy, w.T)
+    st, _ = pond.step(cfg, st, nsteps=3)
+    out, _ = pond.step(cfg, st.clone())
+    gen = torch.Generator(device="cuda").manual_seed(7)
+    wf = torch.randn(out.f.shape, dtype=torch.float64, device="cuda", generator=gen)
+    wg = torch.randn(out.g.shape, dtype=torch.float64, device="cuda", generator=gen)
+    runs = []
+    for lanes in (1, 1, 1, 2, 4):
+        monkeypatch.setenv("POND_ADJOINT_LANES", str(lanes))
+        t = torch.zeros(1, dtype=torch.float64, device="cuda")
+        af, ag = pond.step_adjoint(cfg, st, out, wf, wg, t)
+        torch.cuda.synchronize()
+        runs.append((lanes, af.cpu().numpy(), ag.cpu().numpy(), float(t.item())))
+    _, f0, g0, t0 = runs[0]
+    for lanes, f, g, t in runs[1:]:
+        ef = np.max(np.abs(f - f0)) / np.max(np.abs(f0))
+        eg = np.max(np.abs(g - g0)) / np.max(np.abs(g0))
+        print(f"lanes {lanes}: f {ef:.1e} g {eg:.1e} tau {abs(t - t0) / abs(t0):.1e}", flush=True)
+        assert ef < 1e-13 and eg < 1e-13 and abs(t - t0) <= 1e-13 * abs(t0)
