@@ -11,7 +11,8 @@ error against FP64, the adjoint/forward time ratios and the oracle timed on
 host cores (`cpu_baseline`) are reported beside it.
 
 Other modes (used for profiling, each prints its own line):
-  --kernel-only   FP64 steps only, no replays or baselines (for rocprofv3)
+  --kernel-only   FP64 steps only, then one replay with step statistics for the
+                  pass count and the roofline fraction (for rocprofv3)
   --copy-probe    a plain device copy of known size (HBM counter calibration)
   --adjoint-only  FP64 adjoint of one step at the state after 50 steps, twice
 """
@@ -485,8 +486,16 @@ def main():
     mlups64 = nodes * args.steps / (ms64 * 1e-3) / 1e6
     log(f"[bench] FP64 {ms64 / args.steps:.3f} ms/step (median of {runs}), {mlups64:.1f} MLUPS")
     if args.kernel_only:
+        # the timed window's pass count comes from a replay with step
+        # statistics (the same steps again: a kernel trace holds both)
+        passes = count_passes(cfg64, w, args.steps)
+        roof = alu_roofline(passes["mean_passes"], nodes, ms64 / args.steps, PEAK_FP64_TFLOPS)
         print(json.dumps({"kernel_only": True, "ms_per_step": ms64 / args.steps,
-                          "value": mlups64, "unit": "MLUPS"}), flush=True)
+                          "value": mlups64, "unit": "MLUPS",
+                          "mean_pc_passes": passes["mean_passes"],
+                          "flops_per_launch": roof["flops_per_launch"],
+                          "achieved_tflops": roof["achieved"], "frac": roof["frac"],
+                          "replayed_steps_with_statistics": args.steps}), flush=True)
         return
 
     result = {
