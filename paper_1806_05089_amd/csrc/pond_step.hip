@@ -322,22 +322,24 @@ __device__ __forceinline__ void store_bad(const StepArgs& A, FT* fout, size_t pl
   }
 }
 
-// ---- tail: finishing one node with a group of 16 lanes ----
-// Lane p of the group owns population (i, j) = (p / q, p % q).  The group
-// reduces the corrector moments with butterfly shuffles and gathers the
-// populations of the regauge with shuffles.  Every lane of the wave must call
-// this together (the shuffles span the wave); lanes of a group without a node
-// pass has = false.  Collocation points come from the block's LDS window
-// (pair_value, HBM outside it).  The group's final pass count raises *s_key,
-// the pass maximum of the wave that deferred the node, and, when the step
-// keeps statistics, its bin of the block's pass histogram s_hist.
-template <int Q1, class FT, int WX, int WY, int WN>
-__device__ __forceinline__ void tail_group(const StepArgs& A, const FT* s_f, int wx0, int wy0,
-                                           double uxB, double uyB, double sB, bool has, int X,
-                                           int Y, double ux, double uy, double T, unsigned passes,
-                                           unsigned* s_key, unsigned* s_hist,
-                                           unsigned long long& c_nc, unsigned long long& c_nb,
-                                           unsigned long long& c_sp, unsigned long long& c_mp) {
+// ---- tail: finishing the block's unconverged nodes with groups of 16 lanes ----
+// Lane p of a group owns population (i, j) = (p / q, p % q) of the group's
+// node.  The group reduces the corrector moments with butterfly shuffles and
+// gathers the populations of the regauge with shuffles.  Every lane of the wave
+// runs this together (the shuffles span the wave); each group takes the next
+// node of the block's list (count entries, the next one at *s_next) as soon
+// as its own node has finished, so the groups of a wave do not wait for the
+// wave's slowest node.  Collocation points come from the block's LDS window
+// (pair_value, HBM outside it).  A node's final pass count raises the pass
+// maximum of the wave that deferred it (s_wmax) and, when the step keeps
+// statistics, its bin of the block's pass histogram s_hist.
+template <int Q1, class FT, int WX, int WY, int WN, int TX, int WTX, int WTY>
+__device__ __forceinline__ void tail_wave(const StepArgs& A, const FT* s_f, int wx0, int wy0,
+                                          double uxB, double uyB, double sB, int bx0, int by0,
+                                          unsigned count, const unsigned* s_list,
+                                          unsigned* s_next, unsigned* s_wmax, unsigned* s_hist,
+                                          unsigned long long& c_nc, unsigned long long& c_nb,
+                                          unsigned long long& c_sp, unsigned long long& c_mp) {
   constexpr int Q = Q1 * Q1;
   using L = Lat<Q1>;
   const size_t plane = (size_t)A.nx * A.ny;
@@ -353,14 +355,51 @@ __device__ __forceinline__ void tail_group(const StepArgs& A, const FT* s_f, int
   const double ci = speed_lane<Q1>(pi), cj = speed_lane<Q1>(pj);
   const LagRow Pi = lag_row_lane<Q1>(pi), Pj = lag_row_lane<Q1>(pj);
   const int base = lane & ~15;
-  const size_t node = (size_t)Y * A.nx + X;
-  unsigned flags = 0;
-  bool gdone = !has, bad = false;
+  bool has = false, exhausted = false, gdone = true, bad = false;
+  unsigned passes = 0, flags = 0;
+  int X = 0, Y = 0, lw = 0;
+  size_t node = 0;
   FT fij = FT(0);
-  double rho1 = 0.0, ux1 = ux, uy1 = uy, T1 = T;
+  double ux = 0.0, uy = 0.0, T = L::TL;
+  double rho1 = 0.0, ux1 = 0.0, uy1 = 0.0, T1 = L::TL;
   for (;;) {
+    // a group without a node takes the next entry of the list; a deferred
+    // node's gauge went through its output gauge slot (read with
+    // L1-bypassing loads)
+    if (!has && !exhausted) {
+      unsigned e = 0;
+      if (p == 0) e = atomicAdd(s_next, 1u);
+      e = __shfl(e, base);
+      if (e < count) {
+        const unsigned ent = s_list[e];
+        const int ltid = (int)(ent & 0xFFFF);
+        lw = ltid >> 6;
+        const int ll = ltid & 63;
+        X = bx0 + (lw % (TX / WTX)) * WTX + (ll % WTX);
+        Y = by0 + (lw / (TX / WTX)) * WTY + (ll / WTX);
+        node = (size_t)Y * A.nx + X;
+        passes = ent >> 16;
+        flags = 0;
+        bad = false;
+        gdone = false;
+        has = true;
+        ux = __hip_atomic_load(&A.g_out[node], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        uy = __hip_atomic_load(&A.g_out[plane + node], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        T = __hip_atomic_load(&A.g_out[2 * plane + node], __ATOMIC_RELAXED,
+                              __HIP_MEMORY_SCOPE_AGENT);
+        rho1 = 0.0;
+        ux1 = ux;
+        uy1 = uy;
+        T1 = T;
+      } else {
+        exhausted = true;
+      }
+    }
+    if (__all(!has)) break;
+    // one predictor-corrector pass for the groups still iterating
     double s = 0.0;
-    if (!gdone) {
+    const bool iter = has && !gdone;
+    if (iter) {
       ++passes;
       s = sqrt(T * L::inv_TL);
       const double inv_s = 1.0 / s;
@@ -415,7 +454,7 @@ __device__ __forceinline__ void tail_group(const StepArgs& A, const FT* s_f, int
     // a6 over the 16 lanes of the group (compensated pairwise sums; in
     // FP32 the products with the speeds are split exactly as in the one-lane
     // form, and the speeds are held as FP32 pairs)
-    const bool live = !gdone && pop;
+    const bool live = iter && pop;
     FT v[4], er[4];
     {
 #pragma clang fp contract(off)
@@ -444,7 +483,7 @@ __device__ __forceinline__ void tail_group(const StepArgs& A, const FT* s_f, int
         }
       }
     }
-    if (!gdone) {
+    if (iter) {
       const int verdict = corrector<Q1>(A, s, ux, uy, T, double(v[0]) + double(er[0]),
                                         double(v[1]) + double(er[1]), double(v[2]) + double(er[2]),
                                         double(v[3]) + double(er[3]), passes, rho1, ux1, uy1, T1,
@@ -467,45 +506,47 @@ __device__ __forceinline__ void tail_group(const StepArgs& A, const FT* s_f, int
         T = T1;
       }
     }
-    if (__all(gdone)) break;
-  }
-  // a8 + a9 + a10 for the group's node; every lane joins the shuffles
-  FT fr = FT(0);
-  {
-    const double s = sqrt(T * L::inv_TL), s1 = sqrt(T1 * L::inv_TL);
-    const double inv_s1 = 1.0 / s1, r = s * inv_s1;
-    double ry[Q1], rx[Q1];
-    transfer_row_coef<Q1>(Pj, r, (uy - uy1) * inv_s1, ry);  // row l = pj of Ry
-    transfer_row_coef<Q1>(Pi, r, (ux - ux1) * inv_s1, rx);  // row k = pi of Rx
-    FT h = FT(0);  // Hm(pi, l = pj) = sum_j Ry[l][j] F(pi, j)
+    // a8 + a9 + a10 for the groups whose node has finished; every lane
+    // joins the shuffles
+    if (!__any(has && gdone)) continue;
+    FT fr = FT(0);
+    {
+      const double s0 = sqrt(T * L::inv_TL), s1 = sqrt(T1 * L::inv_TL);
+      const double inv_s1 = 1.0 / s1, r = s0 * inv_s1;
+      double ry[Q1], rx[Q1];
+      transfer_row_coef<Q1>(Pj, r, (uy - uy1) * inv_s1, ry);  // row l = pj of Ry
+      transfer_row_coef<Q1>(Pi, r, (ux - ux1) * inv_s1, rx);  // row k = pi of Rx
+      FT h = FT(0);  // Hm(pi, l = pj) = sum_j Ry[l][j] F(pi, j)
 #pragma unroll
-    for (int jj = 0; jj < Q1; ++jj) h += FT(ry[jj]) * __shfl(fij, base + pi * Q1 + jj);
+      for (int jj = 0; jj < Q1; ++jj) h += FT(ry[jj]) * __shfl(fij, base + pi * Q1 + jj);
 #pragma unroll
-    for (int ii = 0; ii < Q1; ++ii) fr += FT(rx[ii]) * __shfl(h, base + ii * Q1 + pj);
-  }
-  if (has) {
-    if (bad) {
-      if (pop) store_bad<Q1, FT>(A, fout, plane, node, p, p + 1);
-      flags |= POND_ITERS_BAD;
-    } else if (pop) {
-      if (A.tape_f) A.tape_f[(size_t)p * plane + node] = double(fij);
-      const FT feq = FT(rho1 * (L::w(pi) * L::w(pj)));
-      fout[(size_t)p * plane + node] = fr + FT(1.0 / A.tau) * (feq - fr);
+      for (int ii = 0; ii < Q1; ++ii) fr += FT(rx[ii]) * __shfl(h, base + ii * Q1 + pj);
+    }
+    if (has && gdone) {
+      if (bad) {
+        if (pop) store_bad<Q1, FT>(A, fout, plane, node, p, p + 1);
+        flags |= POND_ITERS_BAD;
+      } else if (pop) {
+        if (A.tape_f) A.tape_f[(size_t)p * plane + node] = double(fij);
+        const FT feq = FT(rho1 * (L::w(pi) * L::w(pj)));
+        fout[(size_t)p * plane + node] = fr + FT(1.0 / A.tau) * (feq - fr);
+        if (p == 0) {
+          A.g_out[node] = ux1;
+          A.g_out[plane + node] = uy1;
+          A.g_out[2 * plane + node] = T1;
+        }
+      }
       if (p == 0) {
-        A.g_out[node] = ux1;
-        A.g_out[plane + node] = uy1;
-        A.g_out[2 * plane + node] = T1;
+        if (A.iters) A.iters[node] = (uint8_t)((passes & POND_ITERS_MASK) | flags);
+        atomicMax(&s_wmax[lw], passes);
+        if (A.counters) atomicAdd(&s_hist[passes & POND_ITERS_MASK], 1u);
+        c_nc += (flags & POND_ITERS_NONCONVERGED) ? 1 : 0;
+        c_nb += (flags & POND_ITERS_BAD) ? 1 : 0;
+        c_sp += passes;
+        c_mp = passes > c_mp ? passes : c_mp;
       }
     }
-    if (p == 0) {
-      if (A.iters) A.iters[node] = (uint8_t)((passes & POND_ITERS_MASK) | flags);
-      atomicMax(s_key, passes);
-      if (A.counters) atomicAdd(&s_hist[passes & POND_ITERS_MASK], 1u);
-      c_nc += (flags & POND_ITERS_NONCONVERGED) ? 1 : 0;
-      c_nb += (flags & POND_ITERS_BAD) ? 1 : 0;
-      c_sp += passes;
-      c_mp = passes > c_mp ? passes : c_mp;
-    }
+    if (has && gdone) has = false;
   }
 }
 
@@ -1158,31 +1199,10 @@ k_step(StepArgs A) {
       __threadfence_block();
       __syncthreads();
       const unsigned count = s_tail[0];
-      if (count) {
-        for (;;) {
-          unsigned e = 0;
-          if ((lane & 15) == 0) e = atomicAdd(&s_tail[1], 1u);
-          e = __shfl(e, lane & ~15);
-          const bool has = e < count;
-          if (__all(!has)) break;
-          const unsigned ent = has ? s_list[e] : 0u;
-          const int ltid = (int)(ent & 0xFFFF);
-          const int lw = ltid >> 6, ll = ltid & 63;
-          const int tX = bx0 + (lw % (TX / WTX)) * WTX + (ll % WTX);
-          const int tY = by0 + (lw / (TX / WTX)) * WTY + (ll / WTX);
-          double tux = 0.0, tuy = 0.0, tT = L::TL;
-          if (has) {
-            const size_t tnode = (size_t)tY * A.nx + tX;
-            tux = __hip_atomic_load(&A.g_out[tnode], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            tuy = __hip_atomic_load(&A.g_out[plane + tnode], __ATOMIC_RELAXED,
-                                    __HIP_MEMORY_SCOPE_AGENT);
-            tT = __hip_atomic_load(&A.g_out[2 * plane + tnode], __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-          }
-          tail_group<Q1, FT, WX, WY, WN>(A, s_f, wx0, wy0, uxB, uyB, sB, has, tX, tY, tux, tuy, tT,
-                                         ent >> 16, &s_wmax[lw], s_hist, c_nc, c_nb, c_sp, c_mp);
-        }
-      }
+      if (count)
+        tail_wave<Q1, FT, WX, WY, WN, TX, WTX, WTY>(A, s_f, wx0, wy0, uxB, uyB, sB, bx0, by0,
+                                                     count, s_list, &s_tail[1], s_wmax, s_hist,
+                                                     c_nc, c_nb, c_sp, c_mp);
     }
     if (A.counters) {
 #pragma unroll
