@@ -54,10 +54,36 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def source_digest():
+def code_text(src: str) -> str:
+    """C++ source without its comments and with runs of whitespace collapsed:
+    what the compiler sees, so that editing a comment keeps a digest."""
+    out, i, n = [], 0, len(src)
+    while i < n:
+        if src.startswith("//", i):
+            j = src.find("\n", i)
+            i = n if j < 0 else j
+        elif src.startswith("/*", i):
+            j = src.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+            out.append(" ")
+        elif src[i] == '"':  # string literal, copied as it is
+            j = i + 1
+            while j < n and src[j] != '"':
+                j += 2 if src[j] == "\\" else 1
+            out.append(src[i:j + 1])
+            i = j + 1
+        else:
+            out.append(src[i])
+            i += 1
+    return " ".join("".join(out).split())
+
+
+def source_digest(paths=None):
+    """sha256[:16] of the step kernel's sources (comments and layout ignored)."""
     h = hashlib.sha256()
-    for path in STEP_SOURCES:
-        h.update(open(path, "rb").read())
+    for path in (STEP_SOURCES if paths is None else paths):
+        h.update(code_text(open(path, encoding="utf-8").read()).encode())
+        h.update(b"\0")
     return h.hexdigest()[:16]
 
 

@@ -16,8 +16,9 @@
 // to each lane's node); per y speed a column's four rows are read from LDS,
 // contracted with the y row of G_{B->n} and summed with their y weights, and
 // the four x speeds share the result.  A collocation point outside the window
-// is read from HBM and transformed directly with G_{s->n}.  After staging the lanes iterate
-// independently (no further barriers).
+// is read from HBM and transformed directly with G_{s->n}.  After staging the
+// lanes iterate independently up to the bulk-pass cap; nodes still iterating
+// then go to a list that the block's 16-lane groups finish (the tail).
 #include <hip/hip_runtime.h>
 #include <limits.h>
 #include <math.h>

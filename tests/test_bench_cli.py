@@ -29,6 +29,22 @@ def test_host_cpu_and_source_digest():
         "pond_step.hip", "pond_device.hpp", "pond_api.hip"]
 
 
+def test_source_digest_ignores_comments_only(tmp_path):
+    import bench
+    code = 'int f(int x) { // twice\n  return 2 * x; /* block */ }\nconst char* s = "a // b";\n'
+    a = tmp_path / "a.hip"
+    a.write_text(code)
+    b = tmp_path / "b.hip"
+    b.write_text(code.replace("// twice", "// doubled").replace("/* block */", "") + "\n\n")
+    c = tmp_path / "c.hip"
+    c.write_text(code.replace("2 * x", "3 * x"))
+    d = tmp_path / "d.hip"
+    d.write_text(code.replace('"a // b"', '"a // c"'))
+    assert bench.source_digest([str(a)]) == bench.source_digest([str(b)])
+    assert bench.source_digest([str(a)]) != bench.source_digest([str(c)])
+    assert bench.source_digest([str(a)]) != bench.source_digest([str(d)])
+
+
 def test_flop_count_per_node_pass():
     import bench
     # 16 populations x 16 points x 42, 8 departure coordinates x 16, 7 x 16
