@@ -7,6 +7,11 @@
 
 namespace pond {
 
+// A double constant split into the nearest FP32 value and the FP32 rounding
+// of the remainder (hi + lo equals it to about 2^-48 relative).
+__host__ __device__ constexpr float split_hi(double a) { return float(a); }
+__host__ __device__ constexpr float split_lo(double a) { return float(a - double(float(a))); }
+
 // ------------------------------------------------------------ speed sets
 // D2Q16: per-axis speeds are the roots of the probabilists' Hermite
 // polynomial He_4, +-sqrt(3 -+ sqrt 6), with Gauss-Hermite weights
@@ -175,12 +180,26 @@ __device__ __forceinline__ double speed_rt(int i) {
 // four-node stencil around the point is symmetric, so the weight is
 // (|u|+1)(|u|-1)(|u|-2)/2 for |u| <= 1, -(|u|-1)(|u|-2)(|u|-3)/6 for
 // 1 < |u| < 2, and the node is outside the stencil (in = false, weight 0)
-// beyond.  Evaluated in FT from |u| (FP32: |u| rounded once).
+// beyond.  Evaluated in FT from |u| (FP32: |u| rounded once).  In FP32 the
+// monomial coefficients -1/6 and -11/6 of the outer weight both round away
+// from zero, which made every outer weight about 8e-8 too small: the
+// weights of a departure point then summed to about 1 - 1.5e-7, a mass loss
+// of that size at every step.  FP32 therefore takes the product form, whose
+// factors |u| - 1, |u| - 2, 3 - |u| are exact for |u| in [1, 2] and whose 1/6
+// enters as a float pair.
 template <class FT>
 __device__ __forceinline__ FT lagrange_weight(double u, bool& in) {
   const FT a = FT(fabs(u));
-  const FT near = fma(fma(fma(FT(0.5), a, FT(-1.0)), a, FT(-0.5)), a, FT(1.0));
-  const FT far = fma(fma(fma(FT(-1.0 / 6.0), a, FT(1.0)), a, FT(-11.0 / 6.0)), a, FT(1.0));
+  FT near, far;
+  if constexpr (sizeof(FT) == 4) {
+    const FT t = (a - 1.0f) * (a - 2.0f);
+    near = t * fmaf(0.5f, a, 0.5f);
+    const FT p = t * (3.0f - a);
+    far = fmaf(p, split_lo(1.0 / 6.0), p * split_hi(1.0 / 6.0));
+  } else {
+    near = fma(fma(fma(FT(0.5), a, FT(-1.0)), a, FT(-0.5)), a, FT(1.0));
+    far = fma(fma(fma(FT(-1.0 / 6.0), a, FT(1.0)), a, FT(-11.0 / 6.0)), a, FT(1.0));
+  }
   in = a < FT(2.0);
   const FT w = a <= FT(1.0) ? near : far;
   return in ? w : FT(0);
@@ -314,11 +333,6 @@ __device__ __forceinline__ void dot2_acc(R& s, R& c, R a_hi, R a_lo, R x) {
   c += ((s - (t - bp)) + (p - bp)) + fma(a_lo, x, pe);
   s = t;
 }
-
-// A double constant split into the nearest FP32 value and the FP32 rounding
-// of the remainder (hi + lo equals it to about 2^-48 relative).
-__host__ __device__ constexpr float split_hi(double a) { return float(a); }
-__host__ __device__ constexpr float split_lo(double a) { return float(a - double(float(a))); }
 
 // LDS layout of the staged window: the Q values of a window node are kept in
 // groups of G = 16 / sizeof(FT) populations whose values are adjacent, so
