@@ -189,7 +189,7 @@ def full_run(w, steps=2000, check_steps=(10, 100, 2000)):
         out[k]["iter_hist_node_steps"] = trim_hist(acc[k]["hist"])
         out[k]["roofline"] = alu_roofline(mp, nodes, out[k]["ms_per_step"], peaks[k])
     out["f32_mixed"]["roofline"]["peak_note"] = (
-        "78.6 TFLOP/s: the rate of the unpacked FP32 vector FMAs this build issues "
+        "78.6 TFLOP/s: the rate of the unpacked FP32 vector FMAs the library issues "
         "(packed FP32 is compiled out); against the 157.3 TFLOP/s packed peak the fraction "
         "is half")
     out["speedup_fp32_vs_fp64"] = out["f32_mixed"]["value"] / out["f64"]["value"]
@@ -586,7 +586,7 @@ def main():
             fp32["roofline"]["frac_vs_packed_fp32_peak"] = (
                 fp32["roofline"]["achieved"] / PEAK_FP32_TFLOPS)
             fp32["roofline"]["peak_note"] = (
-                "peak = 78.6 TFLOP/s, the unpacked FP32 vector FMA rate this build issues "
+                "peak = 78.6 TFLOP/s, the unpacked FP32 vector FMA rate the library issues "
                 "(packed FP32 is compiled out); frac_vs_packed_fp32_peak uses 157.3")
         log("[bench] FP32 vs FP64 at equal passes; other configs; 2048^2")
         fp32["speedup_at_equal_passes"] = fixed_pass_speedup(w)

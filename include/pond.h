@@ -57,7 +57,7 @@ enum {
   POND_E_ALIAS = -3,       /* input and output buffers overlap                */
   POND_E_STATE = -4,       /* pond_init found rho <= 0, T <= 0 or non-finite  */
   POND_E_HIP = -5,         /* a HIP runtime call failed                       */
-  POND_E_UNSUPPORTED = -6  /* valid request that this build does not provide  */
+  POND_E_UNSUPPORTED = -6  /* valid request that the library does not provide */
 };
 
 enum { POND_F64 = 0, POND_F32_MIXED = 1 };
