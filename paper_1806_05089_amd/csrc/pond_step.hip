@@ -585,14 +585,15 @@ __device__ void order_tiles(const uint16_t* keys, unsigned* order, unsigned ntil
   for (unsigned t = tid; t < ntiles; t += NT) order[atomicAdd(&start[keys[t]], 1u)] = t;
 }
 
-// Blocks per CU the registers are sized for: two (2 waves per SIMD, 256
-// VGPRs); FP32-mixed D2Q9 three (168 VGPRs, 30 spilled, measured 8-10 %
-// faster than two).
+// Waves per SIMD the registers are sized for (the launch bound's second
+// argument): two (256 VGPRs: one 8-wave FP64 block or two 4-wave FP32-mixed
+// blocks per CU); FP32-mixed D2Q9 three (168 VGPRs, 33 spilled, three
+// blocks per CU, measured 8-10 % faster than two).
 template <int Q1, class FT>
-constexpr int kStepBlocksPerCU = sizeof(FT) == 4 && Q1 == 3 ? 3 : 2;
+constexpr int kStepWavesPerSIMD = sizeof(FT) == 4 && Q1 == 3 ? 3 : 2;
 
 template <int Q1, class FT, int TX, int TY, int H>
-__global__ void __launch_bounds__(TX * TY, (kStepBlocksPerCU<Q1, FT>))
+__global__ void __launch_bounds__(TX * TY, (kStepWavesPerSIMD<Q1, FT>))
 k_step(StepArgs A) {
   constexpr int Q = Q1 * Q1;
   using L = Lat<Q1>;
