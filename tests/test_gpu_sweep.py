@@ -1,0 +1,55 @@
+"""Seeded sweep of small step configurations against the oracle.
+
+Each case draws (from its own seed) a grid of 1..90 by 1..70 nodes, the
+lattice, the precision, the edge treatment per axis, the flow's Mach number
+and a fixed pass count, builds a smooth random state on it and compares one HIP
+step with the oracle's, element by element: FP64 within 1e-12 of the field
+scale, FP32-mixed within the one-step FP32 bound of the parity tests (2e-6).
+Ragged tiles, strips, single rows and columns, and grids smaller than one
+wave all come up.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1806_05089_amd import pond, workloads
+from tests.parity import state_errors
+
+pytestmark = pytest.mark.gpu
+
+
+def _case(seed):
+    rng = np.random.default_rng(1000 + seed)
+    nx = int(rng.integers(1, 91))
+    ny = int(rng.integers(1, 71))
+    q = int(rng.choice([3, 4]))
+    prec = int(rng.choice([pond.POND_F64, pond.POND_F32_MIXED]))
+    bc_x, bc_y = int(rng.integers(0, 2)), int(rng.integers(0, 2))
+    npass = int(rng.integers(1, 4))
+    T0 = 1.0 if q == 4 else 1.0 / 3.0
+    mach = float(rng.uniform(0.0, 0.8))
+    w = workloads.random_smooth(nx, ny, seed=seed, mach=mach, T0=T0)
+    return w, q, prec, bc_x, bc_y, npass
+
+
+@pytest.mark.parametrize("seed", range(16))
+def test_random_configuration_vs_oracle(gpu, seed):
+    w, q, prec, bc_x, bc_y, npass = _case(seed)
+    ny, nx = w.shape
+    print(f"seed {seed}: {nx}x{ny} q {q} precision {prec} bc ({bc_x},{bc_y}) passes {npass}",
+          flush=True)
+    cfg = pond.PondConfig(nx=nx, ny=ny, q1d=q, precision=prec, isothermal=w.isothermal,
+                          bc_x=bc_x, bc_y=bc_y, tau=w.tau, fixed_iter=npass)
+    st = pond.init(cfg, w.rho, w.ux, w.uy, w.T)
+    out, _ = pond.step(cfg, st)
+    f0, g0 = oracle.init(w.rho, w.ux, w.uy, w.T, q=q)
+    oc = oracle.OracleConfig(q=q, isothermal=w.isothermal, bc_x=bc_x, bc_y=bc_y,
+                             max_iter=cfg.max_iter, fixed_iter=npass, seed_mode=0,
+                             tau=w.tau, eps_abs=cfg.eps_abs, eps_rel=cfg.eps_rel)
+    fo, go, io, _ = oracle.step(f0, g0, oc)
+    fg, gg = out.f.double().cpu().numpy(), out.g.cpu().numpy()
+    assert np.array_equal(out.iters.cpu().numpy() & pond.POND_ITERS_MASK, io & pond.POND_ITERS_MASK)
+    u_scale = max(1e-3, float(np.max(np.hypot(w.ux, w.uy))), float(np.sqrt(np.max(w.T))))
+    errs = state_errors(fg, gg, fo, go, u_scale=u_scale, T_scale=float(np.max(w.T)))
+    tol = 1e-12 if prec == pond.POND_F64 else 2e-6
+    assert max(errs.values()) < tol, errs
