@@ -131,6 +131,11 @@ int pond_init(const pond_config* cfg, const double* rho, const double* ux, const
  * (FP32 machine epsilon) is rejected with POND_E_INVALID (the paper's FP64
  * values 1e-12 / 1e-10 would run every node to max_iter); the same holds for
  * pond_step_record and both adjoint calls.
+ * Tuning (environment, read once per process; results agree to rounding):
+ * POND_BULK_CAP = n sets how many passes a node runs one lane per node before
+ * an unconverged node is finished by 16 lanes (default D2Q16 FP64 7, D2Q9
+ * FP64 9, FP32-mixed 5; n >= max_iter: never); POND_ADJOINT_LANES = 1, 2 or 4
+ * fixes the lanes per node of the adjoint kernels (default: by grid size).
  */
 int pond_step(const pond_config* cfg, pond_state* in, pond_state* out, int32_t nsteps,
               void* hip_stream, pond_stats* stats);
