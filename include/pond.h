@@ -134,7 +134,7 @@ int pond_init(const pond_config* cfg, const double* rho, const double* ux, const
  * Tuning (environment, read once per process; results agree to rounding):
  * POND_BULK_CAP = n sets how many passes a node runs one lane per node before
  * an unconverged node is finished by 16 lanes (default D2Q16 FP64 7, D2Q9
- * FP64 9, FP32-mixed 5; n >= max_iter: never); POND_ADJOINT_LANES = 1, 2 or 4
+ * FP64 9, FP32-mixed 5; 0 or n >= max_iter: never); POND_ADJOINT_LANES = 1, 2 or 4
  * fixes the lanes per node of the adjoint kernels (default: by grid size).
  */
 int pond_step(const pond_config* cfg, pond_state* in, pond_state* out, int32_t nsteps,
