@@ -11,8 +11,9 @@ error against FP64, the adjoint/forward time ratios and the oracle timed on
 host cores (`cpu_baseline`) are reported beside it.
 
 Other modes (used for profiling, each prints its own line):
-  --kernel-only   FP64 steps only, then one replay with step statistics for the
-                  pass count and the roofline fraction (for rocprofv3)
+  --kernel-only   FP64 steps only (FP32-mixed with --kernel-precision f32), then
+                  one replay with step statistics for the pass count and the
+                  roofline fraction (for rocprofv3)
   --copy-probe    a plain device copy of known size (HBM counter calibration)
   --adjoint-only  FP64 adjoint of one step at the state after 50 steps, twice
 """
@@ -482,6 +483,8 @@ def main():
     p.add_argument("--cpu-sample", type=int, default=1000000)
     p.add_argument("--no-pass-count", action="store_true")
     p.add_argument("--kernel-only", action="store_true")
+    p.add_argument("--kernel-precision", choices=("f64", "f32"), default="f64",
+                   help="precision of the --kernel-only steps")
     p.add_argument("--copy-probe", action="store_true")
     p.add_argument("--adjoint-only", action="store_true")
     p.add_argument("--runs", type=int, default=5, help="timed runs of K steps; value = median")
@@ -505,6 +508,22 @@ def main():
 
     w = workloads.riemann2d(args.size, seed=3)
     nodes = args.size * args.size
+    if args.kernel_only and args.kernel_precision == "f32":
+        cfg32 = make_cfg(w, pond.POND_F32_MIXED)
+        log(f"[bench] FP32-mixed {args.size}^2, warmup {args.warmup}, steps {args.steps}")
+        ms32, _, _, _ = timed_steps(cfg32, w, args.steps, args.warmup, 1)
+        passes = count_passes(cfg32, w, args.steps)
+        # rate of the unpacked FP32 FMAs the kernels issue (packed FP32 is compiled out)
+        roof = alu_roofline(passes["mean_passes"], nodes, ms32 / args.steps, PEAK_FP64_TFLOPS)
+        print(json.dumps({"kernel_only": True, "precision": "f32_mixed",
+                          "ms_per_step": ms32 / args.steps,
+                          "value": nodes * args.steps / (ms32 * 1e-3) / 1e6, "unit": "MLUPS",
+                          "mean_pc_passes": passes["mean_passes"],
+                          "flops_per_launch": roof["flops_per_launch"],
+                          "achieved_tflops": roof["achieved"], "frac": roof["frac"],
+                          "peak_tflops": PEAK_FP64_TFLOPS,
+                          "replayed_steps_with_statistics": args.steps}), flush=True)
+        return
     cfg64 = make_cfg(w, pond.POND_F64)
     runs = 1 if args.kernel_only else args.runs
     log(f"[bench] FP64 {args.size}^2, warmup {args.warmup}, steps {args.steps}, runs {runs}")

@@ -16,6 +16,18 @@ def test_more_than_one_gpu_exits_with_a_message():
     assert r.stdout.strip() == "" or not r.stdout.strip().startswith("{")
 
 
+def test_kernel_precision_option_parses():
+    # parsed before the GPU check: without a GPU the run stops there (exit 2)
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--kernel-only",
+                        "--kernel-precision", "f32", "--steps", "2"],
+                       capture_output=True, text=True, timeout=300, cwd=ROOT)
+    assert r.returncode == 2 and "needs a GPU" in r.stderr, r.stderr
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--kernel-only",
+                        "--kernel-precision", "f16"], capture_output=True, text=True,
+                       timeout=300, cwd=ROOT)
+    assert r.returncode == 2 and "invalid choice" in r.stderr
+
+
 def test_host_cpu_and_source_digest():
     import bench
     h = bench.host_cpu()
