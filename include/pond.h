@@ -26,9 +26,9 @@
  *   - Library-held device memory: the first pond_init / pond_step /
  *     pond_step_adjoint on a (device, stream) pair allocates and zeroes a small
  *     slot for it (step statistics, the step kernel's tile queue, and one cost
- *     key and one order entry per tile of 32 x 16 nodes, 32 x 8 in FP32-mixed
- *     mode: 6 bytes per tile, about 12 KiB at 1024^2, grown after a stream
- *     synchronisation when a larger grid appears); it is held until the
+ *     key and one order entry per tile of 32 x 16 nodes for D2Q16 in FP64,
+ *     32 x 8 otherwise: 6 bytes per tile, 12-24 KiB at 1024^2, grown after a
+ *     stream synchronisation when a larger grid appears); it is held until the
  *     process ends.  A step leaves its tiles' costs there, and the next step
  *     on the same stream takes the costliest tiles first: a scheduling hint
  *     only, results do not depend on that order (every call is a pure
@@ -232,8 +232,8 @@ int pond_step_adjoint_recorded(const pond_config* cfg, const pond_state* in,
  * hipMalloc / hipFree and allocates nothing through any library.  Its step
  * counters, tile queue and tile cost/order arrays live in one fixed device
  * array of the library (about 386 KiB per GPU, held until the process ends),
- * sized for at most 65,536 step tiles (tiles of 32 x 16 nodes in POND_F64,
- * 32 x 8 in POND_F32_MIXED: any grid up to 4096 x 4096); a larger grid is
+ * sized for at most 65,536 step tiles (tiles of 32 x 16 nodes for D2Q16 in
+ * POND_F64, 32 x 8 otherwise: any grid up to 4096 x 4096); a larger grid is
  * rejected with POND_E_INVALID.  The queue is cleared by a fill kernel at
  * every call (no memset).  Every call on one GPU shares that GPU's array:
  * calls that overlap on one GPU (different streams, or threads) race and are

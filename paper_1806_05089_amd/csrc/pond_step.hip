@@ -586,9 +586,10 @@ __device__ void order_tiles(const uint16_t* keys, unsigned* order, unsigned ntil
 }
 
 // Waves per SIMD the registers are sized for (the launch bound's second
-// argument): two (256 VGPRs: one 8-wave FP64 block or two 4-wave FP32-mixed
+// argument): two (256 VGPRs: one 8-wave D2Q16 FP64 block or two 4-wave
 // blocks per CU); FP32-mixed D2Q9 three (168 VGPRs, 33 spilled, three
-// blocks per CU, measured 8-10 % faster than two).
+// blocks per CU, measured 8-10 % faster than two; D2Q9 FP64 at three spills
+// 139 registers).
 template <int Q1, class FT>
 constexpr int kStepWavesPerSIMD = sizeof(FT) == 4 && Q1 == 3 ? 3 : 2;
 
@@ -1260,15 +1261,17 @@ k_step(StepArgs A) {
   }
 }
 
-// Tile shapes (TX x TY nodes per block, halo H).  FP64: 32 x 16 nodes, for
-// D2Q16 a 42 x 26 window of 140 KiB of LDS (one block of 8 waves per CU, 2
-// waves per SIMD).  FP32-mixed: 32 x 8 nodes, a 42 x 18 window of 48 KiB,
-// two blocks of 4 waves per CU (2 waves per SIMD; smaller tiles balance the
-// passes better than 32 x 16, and 3 waves per SIMD with registers capped at
-// 168 measured slower once two y speeds share a column walk).
+// Tile shapes (TX x TY nodes per block, halo H).  D2Q16 FP64: 32 x 16
+// nodes, a 42 x 26 window of 140 KiB of LDS (one block of 8 waves per CU, 2
+// waves per SIMD).  Otherwise 32 x 8 nodes: D2Q16 FP32-mixed a 42 x 18
+// window of 48 KiB, two blocks of 4 waves per CU (2 waves per SIMD; smaller
+// tiles balance the passes better than 32 x 16, and 3 waves per SIMD with
+// registers capped at 168 measured slower once two y speeds share a column
+// walk); D2Q9 FP64 a 40 x 16 window of 51 KiB, two blocks per CU (about 1 %
+// faster than one block on 32 x 16 tiles); D2Q9 FP32-mixed three blocks.
 template <int Q1, class FT>
 struct StepTile {
-  static constexpr int TX = 32, TY = sizeof(FT) == 8 ? 16 : 8, H = Q1 == 4 ? 5 : 4;
+  static constexpr int TX = 32, TY = sizeof(FT) == 8 && Q1 == 4 ? 16 : 8, H = Q1 == 4 ? 5 : 4;
 };
 
 // Persistent grid: as many blocks as the device holds at once (CUs x blocks

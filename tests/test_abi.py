@@ -272,3 +272,8 @@ def test_step_noalloc_argument_checks(lib):
     assert lib.pond_step_noalloc(C.byref(big), C.byref(s_in), C.byref(s_out), 1, None,
                                  None) == _lib.POND_E_INVALID
     assert "scratch" in lib.pond_last_error().decode()
+    # D2Q9 in FP64 steps on 32 x 8 tiles too; D2Q16 FP64 on 32 x 16 fits
+    big9 = _cfg(nx=4096, ny=4100, q1d=3)
+    assert lib.pond_step_noalloc(C.byref(big9), C.byref(s_in), C.byref(s_out), 1, None,
+                                 None) == _lib.POND_E_INVALID
+    assert "scratch" in lib.pond_last_error().decode()
