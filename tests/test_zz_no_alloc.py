@@ -34,14 +34,15 @@ def _noalloc_abi(cfg, a, b, nsteps, stats):
     return st
 
 
+@pytest.mark.parametrize("q", [4, 3])
 @pytest.mark.parametrize("prec", [pond.POND_F64, pond.POND_F32_MIXED])
-def test_noalloc_matches_step_two_calls_second_smaller(gpu, prec):
-    kw = dict(precision=prec)
+def test_noalloc_matches_step_two_calls_second_smaller(gpu, prec, q):
+    kw = dict(precision=prec, q1d=q)
     if prec == pond.POND_F32_MIXED:
         kw.update(eps_abs=1e-6, eps_rel=1e-5)
     for n, nsteps in ((200, 3), (72, 2)):
-        print(f"case noalloc prec {prec} grid {n} nsteps {nsteps}", flush=True)
-        w = workloads.riemann2d(n, seed=3)
+        print(f"case noalloc q {q} prec {prec} grid {n} nsteps {nsteps}", flush=True)
+        w = workloads.riemann2d(n, seed=3, T_scale=1.0 if q == 4 else 1.0 / 3.0)
         cfg = _cfg(w, **kw)
         ref_in = pond.init(cfg, w.rho, w.ux, w.uy, w.T)
         ref, ref_stats = pond.step(cfg, ref_in, nsteps=nsteps, stats=True)
