@@ -156,7 +156,6 @@ template <int Q1, class FT, int WX, int WY, int WN>
 __device__ __forceinline__ FT pair_value(const StepArgs& A, const FT* s_f, int wx0, int wy0, int gx,
                                          int gy, const FT* gbx, const FT* gby, const LagRow& Pi,
                                          const LagRow& Pj, double ux, double uy, double inv_s) {
-  using L = Lat<Q1>;
   const int lx = gx - wx0, ly = gy - wy0;
   FT t = FT(0);
   if ((unsigned)lx < (unsigned)WX && (unsigned)ly < (unsigned)WY) {
