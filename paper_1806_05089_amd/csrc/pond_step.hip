@@ -605,26 +605,41 @@ k_step(StepArgs A) {
   __shared__ unsigned s_list[NT];  // deferred nodes: local index | passes << 16
   __shared__ unsigned s_tail[2];   // list length, next entry to take
   __shared__ unsigned s_tile;
+  __shared__ unsigned s_g;             // queue position of the current tile
+  __shared__ unsigned s_pref, s_pref_tile;  // next tile taken ahead (s_pref: position or ~0)
+  __shared__ unsigned s_arrive;        // waves done with the bulk passes of the tile
   __shared__ unsigned s_last;          // this block is the last one out
   __shared__ unsigned s_wmax[TS::NW];  // per wave: maximum passes of its nodes
   __shared__ unsigned s_hist[POND_ITERS_MASK + 1];  // nodes per pass count (statistics)
 
   const int tid = threadIdx.x;
+  // D2Q16 blocks take their next tile ahead (below); measured neutral to
+  // slower for D2Q9
+  constexpr bool kTakeAhead = Q1 == 4;
   const int ntx = (A.nx + TX - 1) / TX;
   const unsigned ntiles = (unsigned)ntx * (unsigned)((A.ny + TY - 1) / TY);
   const bool keyed = A.tile_keys && ntiles <= A.tile_cap;  // tile arrays fit this grid
   if (tid < TS::NW) s_wmax[tid] = 0u;
   if (tid <= POND_ITERS_MASK) s_hist[tid] = 0u;
+  if (tid == 0) s_pref = ~0u;
 
   // Persistent blocks: each block takes tiles from the queue until it is
   // empty, so the cost spread between tiles (passes cluster along fronts) is
   // balanced over all CUs without the hardware dispatcher.
   for (;;) {
     if (tid == 0) {
-      const unsigned g = atomicAdd(&A.queue->next, 1u);
-      s_tile = (keyed && A.tile_order && g < ntiles) ? A.tile_order[g] : g;
+      if (kTakeAhead && s_pref != ~0u) {  // taken while the previous tile finished
+        s_g = s_pref;
+        s_tile = s_pref_tile;
+        s_pref = ~0u;
+      } else {
+        const unsigned g = atomicAdd(&A.queue->next, 1u);
+        s_g = g;
+        s_tile = (keyed && A.tile_order && g < ntiles) ? A.tile_order[g] : g;
+      }
     }
     if (tid < 2) s_tail[tid] = 0u;
+    if (tid == 2) s_arrive = 0u;
     __syncthreads();
     const unsigned tile = s_tile;
     if (tile >= ntiles) break;
@@ -1197,6 +1212,16 @@ k_step(StepArgs A) {
         A.g_out[2 * plane + node] = T;
         const unsigned slot = atomicAdd(&s_tail[0], 1u);
         s_list[slot] = (unsigned)tid | (passes << 16);
+      }
+      // The first wave done with its bulk passes takes the block's next tile
+      // from the queue while the others finish (its wait for the queue is
+      // then off the block's path), unless the queue is within two tiles per
+      // block of its end, where a held tile would wait for this block.
+      if (kTakeAhead && lane == 0 && atomicAdd(&s_arrive, 1u) == 0u &&
+          s_g + 2u * gridDim.x < ntiles) {
+        const unsigned gn = atomicAdd(&A.queue->next, 1u);
+        s_pref_tile = (keyed && A.tile_order && gn < ntiles) ? A.tile_order[gn] : gn;
+        s_pref = gn;
       }
       __threadfence_block();
       __syncthreads();
