@@ -608,20 +608,28 @@ k_step(StepArgs A) {
   __shared__ unsigned s_g;             // queue position of the current tile
   __shared__ unsigned s_pref, s_pref_tile;  // next tile taken ahead (s_pref: position or ~0)
   __shared__ unsigned s_arrive;        // waves done with the bulk passes of the tile
+  // seed gauges (u_x, u_y, T rows of the tile) of the tile taken ahead, and that tile
+  __shared__ __align__(16) double s_seed[Q1 == 4 && sizeof(FT) == 8 ? 3 * TY * TX : 2];
+  __shared__ unsigned s_seed_tile;
   __shared__ unsigned s_last;          // this block is the last one out
   __shared__ unsigned s_wmax[TS::NW];  // per wave: maximum passes of its nodes
   __shared__ unsigned s_hist[POND_ITERS_MASK + 1];  // nodes per pass count (statistics)
 
   const int tid = threadIdx.x;
-  // D2Q16 blocks take their next tile ahead (below); measured neutral to
-  // slower for D2Q9
+  // D2Q16 blocks take their next tile ahead (below; measured neutral to
+  // slower for D2Q9), in FP64 with its seed gauges (1-2 % slower in
+  // FP32-mixed)
   constexpr bool kTakeAhead = Q1 == 4;
+  constexpr bool kStageSeeds = kTakeAhead && sizeof(FT) == 8;
   const int ntx = (A.nx + TX - 1) / TX;
   const unsigned ntiles = (unsigned)ntx * (unsigned)((A.ny + TY - 1) / TY);
   const bool keyed = A.tile_keys && ntiles <= A.tile_cap;  // tile arrays fit this grid
   if (tid < TS::NW) s_wmax[tid] = 0u;
   if (tid <= POND_ITERS_MASK) s_hist[tid] = 0u;
-  if (tid == 0) s_pref = ~0u;
+  if (tid == 0) {
+    s_pref = ~0u;
+    s_seed_tile = ~0u;
+  }
 
   // Persistent blocks: each block takes tiles from the queue until it is
   // empty, so the cost spread between tiles (passes cluster along fronts) is
@@ -661,11 +669,19 @@ k_step(StepArgs A) {
     // a1: seed gauge (eqs. 7-8) or the alternative seeds.
     double ux = 0.0, uy = 0.0, T = L::TL;
     size_t node = 0;
+    const bool seeds_staged = kStageSeeds && s_seed_tile == tile;
     if (active) {
       node = (size_t)Y * A.nx + X;
-      ux = gin[node];
-      uy = gin[plane + node];
-      T = gin[2 * plane + node];
+      if (seeds_staged) {
+        const int k = (Y - by0) * TX + (X - bx0);
+        ux = s_seed[k];
+        uy = s_seed[TY * TX + k];
+        T = s_seed[2 * TY * TX + k];
+      } else {
+        ux = gin[node];
+        uy = gin[plane + node];
+        T = gin[2 * plane + node];
+      }
       if (A.seed_mode == 1) {
         ux = 0.0;
         uy = 0.0;
@@ -1217,11 +1233,44 @@ k_step(StepArgs A) {
       // from the queue while the others finish (its wait for the queue is
       // then off the block's path), unless the queue is within two tiles per
       // block of its end, where a held tile would wait for this block.
-      if (kTakeAhead && lane == 0 && atomicAdd(&s_arrive, 1u) == 0u &&
-          s_g + 2u * gridDim.x < ntiles) {
-        const unsigned gn = atomicAdd(&A.queue->next, 1u);
-        s_pref_tile = (keyed && A.tile_order && gn < ntiles) ? A.tile_order[gn] : gn;
-        s_pref = gn;
+      // The same wave copies that tile's seed gauges into LDS with direct
+      // global-to-LDS loads (no registers held; full tiles on an even-width,
+      // 16-byte aligned gauge array only), so that the tile starts without
+      // that read either.
+      if constexpr (kTakeAhead) {
+        unsigned first = 0u;
+        if (lane == 0) first = atomicAdd(&s_arrive, 1u) == 0u && s_g + 2u * gridDim.x < ntiles;
+        if (__shfl(first, 0)) {
+          unsigned tn = 0u;
+          if (lane == 0) {
+            const unsigned gn = atomicAdd(&A.queue->next, 1u);
+            tn = (keyed && A.tile_order && gn < ntiles) ? A.tile_order[gn] : gn;
+            s_pref_tile = tn;
+            s_pref = gn;
+          }
+          tn = __shfl(tn, 0);
+          const int tyn = (int)(tn / (unsigned)ntx), txn = (int)tn - tyn * ntx;
+          const int bxn = txn * TX, byn = tyn * TY;
+          const bool dma = kStageSeeds && tn < ntiles && bxn + TX <= A.nx && byn + TY <= A.ny &&
+                           (A.nx & 1) == 0 && (reinterpret_cast<uintptr_t>(gin) & 15u) == 0u;
+          if (dma) {
+            // rows r = 0 .. 3 TY - 1 (gauge component r / TY, tile row r % TY) of TX
+            // doubles; one load moves 64 lanes x 16 bytes = four rows, lane l to
+            // LDS bytes 16 l onwards
+            static_assert(TX == 32 && (3 * TY) % 4 == 0, "four gauge rows per load");
+            const int rr = lane >> 4, cc = (lane & 15) * 2;
+#pragma unroll 1
+            for (int k = 0; k < 3 * TY / 4; ++k) {
+              const int r = 4 * k + rr, comp = r / TY, ly = r - comp * TY;
+              const double* src = gin + (size_t)comp * plane + (size_t)(byn + ly) * A.nx + bxn + cc;
+              __builtin_amdgcn_global_load_lds(
+                  (const void __attribute__((address_space(1)))*)src,
+                  (void __attribute__((address_space(3)))*)(s_seed + 4 * k * TX), 16, 0, 0);
+            }
+            __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): the copies are in LDS
+          }
+          if (lane == 0) s_seed_tile = dma ? tn : ~0u;
+        }
       }
       __threadfence_block();
       __syncthreads();
