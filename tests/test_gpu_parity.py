@@ -511,6 +511,27 @@ def test_tile_arrays_across_lattices_and_grids(gpu):
             assert torch.equal(x, y)
 
 
+@pytest.mark.parametrize("prec", [pond.POND_F64, pond.POND_F32_MIXED])
+def test_results_independent_of_tile_order_1024(gpu, prec):
+    """At 1024^2 (over two tiles per block in the queue) a block takes its next
+    tile, and in FP64 that tile's seed gauges, while it finishes the current
+    one; which tiles go that way depends on the tile order.  The same
+    adaptive steps twice on one stream, the second starting from the order
+    the first left, agree bit for bit."""
+    w = workloads.riemann2d(1024, seed=3)
+    kw = dict(precision=prec, max_iter=20)
+    if prec == pond.POND_F32_MIXED:
+        kw.update(eps_abs=1e-6, eps_rel=1e-5)
+    cfg = _cfg(w, **kw)
+    outs = []
+    for _ in range(2):
+        st = pond.init(cfg, w.rho, w.ux, w.uy, w.T)
+        out, _ = pond.step(cfg, st, nsteps=3)
+        outs.append((out.f.clone(), out.g.clone(), out.iters.clone()))
+    for a, b in zip(outs[0], outs[1]):
+        assert torch.equal(a, b)
+
+
 def test_adaptive_results_independent_of_tile_order(gpu):
     """The same adaptive run twice on one stream: the second run starts from
     the tile order the first left behind, and must agree bit for bit."""
